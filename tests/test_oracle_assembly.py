@@ -1,0 +1,235 @@
+"""Pins for the oracle's FP64 assembly and adjoint (CPU only).
+
+Constant coefficients on the (affine) unit box: the weighted rules are exact, so the
+oracle must reproduce the exact Galerkin matrices, here built independently from
+scipy's B-spline basis and numpy's Gauss-Legendre rule (Kronecker products of 1D Gram
+matrices).  Variable coefficients: the method is a quadrature, so only its
+invariants, linearity and convergence laws are pinned; the adjoint is pinned against
+the forward map by the dot-product identity.
+"""
+import numpy as np
+import pytest
+
+import reference_1d as r1
+import structured as st
+import synth_inputs as si
+from oracle import assembly as oa
+
+
+def _kron(mats):
+    out = mats[0]
+    for m in mats[1:]:
+        out = np.kron(out, m)
+    return out
+
+
+def _grid_shape(p, n_el):
+    return [(e + p) * (p + 1) for e in n_el]
+
+
+def _all_ones(p, n_el):
+    return np.ones(_grid_shape(p, n_el))
+
+
+@pytest.mark.parametrize("p,n_el", [
+    (2, (3,)), (3, (4,)), (2, (3, 4)), (2, (5, 8)), (3, (4, 5)), (3, (7, 6)),
+    (2, (3, 4, 5)), (3, (4, 5, 4)),
+])
+def test_constant_coefficients_equal_exact_galerkin(p, n_el):
+    # c = 1, A = I on the unit box: M = kron of 1D mass Grams, K = sum of krons with one
+    # 1D stiffness Gram (exactness of the weighted rules on affine maps)
+    d = len(n_el)
+    tabs = oa.rule_tables(p, n_el)
+    one = _all_ones(p, n_el)
+    M, K = oa.assemble(p, n_el, tabs, c=one, a=[one] * d)
+    n = [e + p for e in n_el]
+    Ms = [r1.gram(p, e) for e in n_el]
+    Ks = [r1.gram(p, e, deriv=True) for e in n_el]
+    M_ref = _kron(Ms)
+    K_ref = sum(_kron([Ks[k] if k == kk else Ms[k] for k in range(d)]) for kk in range(d))
+    Md, Kd = st.to_dense(M, n, p), st.to_dense(K, n, p)
+    assert np.abs(Md - M_ref).max() <= 1e-14 * np.abs(M_ref).max()
+    assert np.abs(Kd - K_ref).max() <= 1e-13 * np.abs(K_ref).max()
+    # every entry of the exact matrices outside the band is zero, so nothing was lost
+    assert np.abs(M_ref[st.to_dense(np.ones_like(M), n, p) == 0]).max(initial=0) == 0
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_one_dimensional_thousand_elements_agree_with_standard_gauss(p):
+    # Sec. 4, first experiment: 1000 uniform elements, weighted rules vs standard Gauss
+    n_el = (1000,)
+    tabs = oa.rule_tables(p, n_el)
+    one = _all_ones(p, n_el)
+    M, K = oa.assemble(p, n_el, tabs, c=one, a=[one])
+    n = [1000 + p]
+    Mg, Kg = r1.gram(p, 1000), r1.gram(p, 1000, deriv=True)
+    dM = np.abs(st.to_dense(M, n, p) - Mg)
+    dK = np.abs(st.to_dense(K, n, p) - Kg)
+    # Entries are O(h) and O(1/h).  Both sides evaluate the basis at FP64 points of
+    # [0, 1], whose absolute resolution near x is ~1.1e-16 x, i.e. up to 1.1e-13 of
+    # one element when h = 1e-3: the agreement is at that level, and ten times
+    # tighter on the first tenth of the domain.
+    assert dM.max() <= 5e-13 * np.abs(Mg).max()
+    assert dK.max() <= 5e-13 * np.abs(Kg).max()
+    assert dM[:100].max() <= 3e-14 * np.abs(Mg).max()
+    assert dK[:100].max() <= 3e-14 * np.abs(Kg).max()
+
+
+@pytest.mark.parametrize("p,n_el", [(2, (5, 6)), (3, (4, 7)), (3, (4, 5, 6))])
+def test_row_sums(p, n_el):
+    # c = 1: row sums of M are prod_k int B_{i_k} = prod_k (t_{i_k+p+1} - t_{i_k}) / (p+1);
+    # any a_k: row sums of K vanish because sum_j grad B_j = 0
+    d = len(n_el)
+    tabs = oa.rule_tables(p, n_el)
+    rng = np.random.default_rng(7)
+    shape = _grid_shape(p, n_el)
+    M, K = oa.assemble(p, n_el, tabs, c=np.ones(shape), a=[rng.uniform(0.5, 2, shape) for _ in range(d)])
+    n = [e + p for e in n_el]
+    idx = st.row_multi(n, np.arange(int(np.prod(n))))
+    want = np.ones(len(idx[0]))
+    for k in range(d):
+        t = r1.knots(p, n_el[k])
+        want *= (t[idx[k] + p + 1] - t[idx[k]]) / (p + 1)
+    np.testing.assert_allclose(M.sum(axis=1), want, rtol=1e-14)
+    assert np.abs(K.sum(axis=1)).max() <= 1e-13 * np.abs(K).max()
+
+
+@pytest.mark.parametrize("p,n_el", [(2, (4, 5)), (3, (5, 4, 4))])
+def test_symmetry_for_constant_coefficients_and_asymmetry_otherwise(p, n_el):
+    d = len(n_el)
+    tabs = oa.rule_tables(p, n_el)
+    n = [e + p for e in n_el]
+    shape = _grid_shape(p, n_el)
+    M, K = oa.assemble(p, n_el, tabs, c=np.full(shape, 2.5), a=[np.full(shape, 1.0 + k) for k in range(d)])
+    Md, Kd = st.to_dense(M, n, p), st.to_dense(K, n, p)
+    assert np.abs(Md - Md.T).max() <= 1e-15 * np.abs(Md).max()
+    assert np.abs(Kd - Kd.T).max() <= 1e-14 * np.abs(Kd).max()
+    # a varying coefficient breaks the symmetry (each row has its own rule)
+    axes = oa.grid_axes(tabs, "c")
+    c = si.fourier_grid(axes, si.fourier_modes(99, 0, d)).numpy()
+    M2, _ = oa.assemble(p, n_el, tabs, c=c)
+    M2d = st.to_dense(M2, n, p)
+    assert np.abs(M2d - M2d.T).max() > 1e-6 * np.abs(M2d).max()
+
+
+def test_linearity():
+    p, n_el = 3, (4, 5, 4)
+    d = 3
+    tabs = oa.rule_tables(p, n_el)
+    rng = np.random.default_rng(11)
+    shape = _grid_shape(p, n_el)
+    c1, c2 = rng.normal(size=shape), rng.normal(size=shape)
+    a1 = [rng.normal(size=shape) for _ in range(d)]
+    a2 = [rng.normal(size=shape) for _ in range(d)]
+    M1, K1 = oa.assemble(p, n_el, tabs, c1, a1)
+    M2, K2 = oa.assemble(p, n_el, tabs, c2, a2)
+    M3, K3 = oa.assemble(p, n_el, tabs, 2 * c1 - 3 * c2, [2 * x - 3 * y for x, y in zip(a1, a2)])
+    np.testing.assert_allclose(M3, 2 * M1 - 3 * M2, atol=1e-14 * np.abs(M3).max())
+    np.testing.assert_allclose(K3, 2 * K1 - 3 * K2, atol=1e-13 * np.abs(K3).max())
+
+
+def test_row_subset_matches_full_assembly():
+    p, n_el = 3, (5, 4, 6)
+    tabs = oa.rule_tables(p, n_el)
+    rng = np.random.default_rng(3)
+    shape = _grid_shape(p, n_el)
+    c = rng.normal(size=shape)
+    a = [rng.normal(size=shape) for _ in range(3)]
+    M, K = oa.assemble(p, n_el, tabs, c, a)
+    rows = rng.choice(M.shape[0], 40, replace=False)
+    Ms, Ks = oa.assemble(p, n_el, tabs, c, a, rows=rows)
+    assert np.array_equal(Ms, M[rows]) and np.array_equal(Ks, K[rows])
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_variable_coefficient_converges_at_first_order(p):
+    # non-constant c: each row's rule integrates c B_i B_j only approximately
+    # (Remark on non-affine maps, Sec. 3); the error against the exact integral
+    # (dense Gauss) shrinks like h
+    errs = []
+    for ne in (16, 32, 64):
+        n_el = (ne, ne)
+        tabs = oa.rule_tables(p, n_el)
+        axes = oa.grid_axes(tabs, "c")
+        c = si.config1_c(axes[0][:, None], axes[1][None, :])
+        M, _ = oa.assemble(p, n_el, tabs, c=c)
+        # exact: c(x, y) = 1 + 0.5 sin sin is a sum of separable terms
+        M1 = r1.gram(p, ne, m=12)
+        S1 = r1.gram(p, ne, m=12, coef=lambda x: np.sin(2 * np.pi * x))
+        n = [ne + p] * 2
+        rows = np.arange(n[0] * n[1])
+        i1, i2 = st.row_multi(n, rows)
+        cols = st.columns(n, p, rows)
+        j1, j2 = np.divmod(np.maximum(cols, 0), n[1])
+        ref = M1[i1[:, None], j1] * M1[i2[:, None], j2] + 0.5 * S1[i1[:, None], j1] * S1[i2[:, None], j2]
+        ref[cols < 0] = 0.0
+        errs.append(np.abs(M - ref).max() / np.abs(ref).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert all(0.8 < r < 1.6 for r in rates), (errs, rates)
+
+
+@pytest.mark.parametrize("p,n_el", [(2, (4, 3)), (3, (4, 5)), (2, (3, 4, 3)), (3, (4, 4, 5))])
+def test_adjoint_dot_product_identity(p, n_el):
+    # <G_M, M(dc)> + <G_K, K(da)> = <dL/dc, dc> + sum_k <dL/da_k, da_k>  (linear maps)
+    d = len(n_el)
+    tabs = oa.rule_tables(p, n_el)
+    shape = _grid_shape(p, n_el)
+    rng = np.random.default_rng(5)
+    dc = rng.normal(size=shape)
+    da = [rng.normal(size=shape) for _ in range(d)]
+    M, K = oa.assemble(p, n_el, tabs, dc, da)
+    n = [e + p for e in n_el]
+    rows = np.arange(int(np.prod(n)))
+    valid = si.slot_valid_mask(n_el, p).numpy()
+    gM = rng.normal(size=M.shape) * valid
+    gK = rng.normal(size=K.shape) * valid
+    lhs = (gM * M).sum() + (gK * K).sum()
+    gc, ga = oa.adjoint(p, n_el, tabs, gM, gK)
+    pts = oa.row_points(p, n_el, rows)
+    rhs = (gc * dc.reshape(-1)[pts]).sum() + sum((ga[k] * da[k].reshape(-1)[pts]).sum() for k in range(d))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + np.abs(gM).sum() * np.abs(M).max())
+    # invalid slots of the upstream gradient are ignored
+    gM2 = gM + np.where(valid, 0.0, 1e3)
+    gc2, _ = oa.adjoint(p, n_el, tabs, gM2, None)
+    assert np.array_equal(gc2, gc)
+
+
+def test_points_partition_the_grid():
+    # each coefficient sample belongs to exactly one row (so the adjoint needs no atomics)
+    for p, n_el in [(2, (3, 5)), (3, (4, 4, 5))]:
+        n = [e + p for e in n_el]
+        pts = oa.row_points(p, n_el, np.arange(int(np.prod(n))))
+        assert np.array_equal(np.sort(pts.reshape(-1)), np.arange(int(np.prod(_grid_shape(p, n_el)))))
+
+
+def test_adjoint_matches_central_differences():
+    # L is linear in the coefficients, so central differences are exact up to rounding
+    p, n_el = 3, (4, 4, 4)
+    tabs = oa.rule_tables(p, n_el)
+    shape = _grid_shape(p, n_el)
+    rng = np.random.default_rng(17)
+    c = rng.uniform(0.5, 1.5, shape)
+    a = [rng.uniform(0.5, 1.5, shape) for _ in range(3)]
+    n = [e + p for e in n_el]
+    valid = si.slot_valid_mask(n_el, p).numpy()
+    SD = 7 ** 3
+    gM = rng.normal(size=(int(np.prod(n)), SD)) * valid
+    gK = rng.normal(size=(int(np.prod(n)), SD)) * valid
+    gc, ga = oa.adjoint(p, n_el, tabs, gM, gK)
+    pts = oa.row_points(p, n_el, np.arange(int(np.prod(n))))
+    h = 1e-6
+    for trial in range(6):
+        r = rng.integers(0, pts.shape[0])
+        q = rng.integers(0, pts.shape[1])
+        off = pts[r, q]
+        field = trial % 4
+        arrs = [c] + a
+        plus = [x.copy() for x in arrs]
+        minus = [x.copy() for x in arrs]
+        plus[field].reshape(-1)[off] += h
+        minus[field].reshape(-1)[off] -= h
+        Mp, Kp = oa.assemble(p, n_el, tabs, plus[0], plus[1:], rows=[r])
+        Mm, Km = oa.assemble(p, n_el, tabs, minus[0], minus[1:], rows=[r])
+        fd = ((gM[r] * (Mp - Mm)).sum() + (gK[r] * (Kp - Km)).sum()) / (2 * h)
+        got = gc[r, q] if field == 0 else ga[field - 1][r, q]
+        assert abs(fd - got) <= 1e-7 * max(1.0, abs(got)), (trial, fd, got)
