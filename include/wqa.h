@@ -1,0 +1,166 @@
+/*
+ * wqa.h -- C ABI of the weighted-quadrature assembly library (libwqa.so) for MI355X.
+ *
+ * The library assembles, row by row, the isogeometric mass matrix
+ *     M_ij = integral of c B_i B_j                                   (eq:Mass)
+ * and stiffness matrix with a diagonal coefficient A = diag(a_1..a_d)
+ *     K_ij = integral of sum_k a_k dB_i/dx_k dB_j/dx_k               (eq:Stiffness)
+ * on the open uniform tensor-product B-spline space of degree p in {2, 3}
+ * (C^1 quadratic, C^2 cubic) and dimension d in {2, 3} (Sec. 2.2, eq:Gmap2,
+ * eq:Gmap3), with the geometry already folded into c and a_k (eq:PullBacks).
+ * Row i is integrated with its own weighted Gaussian rule whose weight function is
+ * B_i (eq:GaussQuadSys for the mass terms, eq:GaussQuadSysStiff for the stiffness
+ * terms), one direction at a time (eq:Decompo), into the (2p+1)^d band of row i
+ * (Fig. 1).  It also evaluates the adjoint of both maps.
+ *
+ * Vocabulary and layouts (all C order):
+ *   n_k       = N_el,k + p basis functions in direction k (eq:DimUni); rows = prod n_k.
+ *   Q         = p + 1 quadrature nodes per row per direction (one per element of the
+ *               row's support for interior rows, Sec. 3).
+ *   S         = 2p + 1 band slots per direction; slot s_k of row i holds column
+ *               j_k = i_k - p + s_k (Fig. 1).
+ *   Row i     = (i_1..i_d), flat index ((i_1 n_2) + i_2) n_3 + i_3 (d = 3).
+ *   Matrix    = [rows][S^d] values ("structured CSR": the column pattern is implicit).
+ *               Slots whose column leaves [0, n_k) in some direction are written 0.
+ *   Grid      = [N_1..N_d] samples, N_k = n_k Q.  The mass coefficient c lives on the
+ *               grid whose direction-k coordinates are the mass-rule nodes of every
+ *               row (row i owns points (i_k Q + q_k)_k).  a_k lives on the grid that
+ *               uses the stiffness-rule nodes in direction k and mass-rule nodes in
+ *               the other directions.  wqa_get_rules returns those coordinates.
+ *
+ * Ownership: every device buffer passed in belongs to the caller; the library owns
+ * the context and its (small) rule tables on host and device.  The assemble calls
+ * never allocate, run asynchronously on the given HIP stream (NULL = default
+ * stream) and return as soon as the work is queued.  A context is not thread-safe;
+ * use one per host thread.
+ *
+ * Errors: every call returns a wqa_status; on failure wqa_last_error() gives a
+ * thread-local message.  Device faults surface at the caller's next synchronization.
+ * Inputs must be finite; non-finite samples propagate into the rows that read them.
+ */
+#ifndef WQA_H
+#define WQA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WQA_ABI_VERSION 1
+
+typedef struct wqa_ctx wqa_ctx;
+
+typedef enum wqa_status {
+    WQA_OK = 0,
+    WQA_EINVAL = -1,        /* bad argument (null pointer, out-of-range value) */
+    WQA_ESTATE = -2,        /* call out of order (no space / no rules / no device) */
+    WQA_EUNSUPPORTED = -3,  /* degree or dimension without rules (p not in {2,3}, d not in {2,3}) */
+    WQA_ERULE = -4,         /* a rule table failed validation, or a rule could not be solved */
+    WQA_EHIP = -5,          /* HIP runtime error (message carries hipGetErrorString) */
+    WQA_ENOMEM = -6         /* host or device allocation failed */
+} wqa_status;
+
+typedef enum wqa_dtype { WQA_F32 = 0, WQA_F64 = 1 } wqa_dtype;
+
+typedef enum wqa_kind { WQA_MASS = 0, WQA_STIFFNESS = 1 } wqa_kind;
+
+/* How the last directional contraction (over the first direction) accumulates in the
+ * FP32 mode.  FP64 calls always accumulate in FP64. */
+typedef enum wqa_final {
+    WQA_FINAL_PLAIN = 0,        /* FP32 fused multiply-adds */
+    WQA_FINAL_COMPENSATED = 1,  /* compensated dot product (error-free products and sums) */
+    WQA_FINAL_F64 = 2           /* FP64 accumulation with the FP64 tables, rounded once */
+} wqa_final;
+
+/* Returns WQA_ABI_VERSION of the loaded library. */
+int wqa_abi_version(void);
+
+/* Message of the last failing call on this thread ("" if none).  The pointer stays
+ * valid until the next library call on the same thread. */
+const char *wqa_last_error(void);
+
+/* Creates a context on HIP device hip_device (>= 0), or a host-only context when
+ * hip_device == -1 (space, rules and tables work; the assemble calls return
+ * WQA_ESTATE).  *out receives the context; destroy it with wqa_destroy. */
+wqa_status wqa_create(wqa_ctx **out, int hip_device);
+
+/* Frees the context and its device tables (after synchronizing its device).  NULL is ignored. */
+void wqa_destroy(wqa_ctx *ctx);
+
+/* Sets the spline space: dimension dim in {2, 3}, degree in {2, 3}, n_elem[dim]
+ * elements per direction (each >= degree + 1), open uniform knots on [0, 1]
+ * (eq:Gmap3).  Discards any rules set before. */
+wqa_status wqa_set_space(wqa_ctx *ctx, int dim, int degree, const int64_t *n_elem);
+
+/* Installs the default rules for both kinds in every direction: the paper's
+ * interior rules (eq:WQquadratic, eq:WQcubic, eq:WQquadraticStiff, eq:WQcubicStiff),
+ * solved on the host by Newton in FP64 from the exactness conditions, translated to
+ * every interior row; and, for the p rows at each end that the paper leaves open
+ * (Remark closing Sec. 3.2), weighted Gaussian rules of at most p+1 nodes solved the
+ * same way (exactness on the row's interacting functions, completed by degree-
+ * elevation monomials), padded to Q nodes with zero weights. */
+wqa_status wqa_set_default_rules(wqa_ctx *ctx);
+
+/* Installs a caller's rule for one kind and direction: nodes[n_dir*q] in [0, 1] and
+ * weights[n_dir*q], row-major by row j then node, q == degree + 1.  The weights
+ * multiply the product of both functions, i.e. the rule claims
+ *     integral phi_i phi_j dx  ~=  sum_m weights[j*q+m] phi_i(x_m) phi_j(x_m)
+ * with phi = B (WQA_MASS) or phi = dB/dx (WQA_STIFFNESS) in parametric units
+ * (eq:GaussQuadSys, eq:GaussQuadSysStiff).  When exact_tol >= 0 every row is
+ * validated: nodes with nonzero weight lie strictly inside supp(B_j) and at least
+ * 1e-9 element widths from any knot, and the relative exactness residual over the
+ * interacting columns is <= exact_tol (WQA_ERULE otherwise, nothing installed).
+ * exact_tol < 0 skips validation.  Copies the arrays; uploads the tables to the
+ * device of a device context. */
+wqa_status wqa_set_rules(wqa_ctx *ctx, wqa_kind kind, int dir, int q,
+                         const double *nodes, const double *weights, double exact_tol);
+
+/* Copies the rule in use for (kind, dir) into nodes[n_dir*q] and weights[n_dir*q]
+ * (either may be NULL).  The nodes are the grid coordinates of direction dir for
+ * every field that uses that kind of rule in that direction. */
+wqa_status wqa_get_rules(const wqa_ctx *ctx, wqa_kind kind, int dir, double *nodes, double *weights);
+
+/* Copies the FP64 contraction table of (kind, dir): out[n_dir][q][S] with
+ * out = weight * phi_j(x) * phi_{j-p+s}(x) at node x of row j (0 for columns
+ * outside the space).  This is what the kernels contract with. */
+wqa_status wqa_get_tables(const wqa_ctx *ctx, wqa_kind kind, int dir, double *out);
+
+/* Sizes of the current space (any pointer may be NULL): rows, S^d slots per row,
+ * Q^d points per row, grid_dims[dim] = N_k. */
+wqa_status wqa_query(const wqa_ctx *ctx, int64_t *n_rows, int64_t *slots_per_row,
+                     int64_t *points_per_row, int64_t *grid_dims);
+
+/* Selects how FP32 calls accumulate the last directional pass (default
+ * WQA_FINAL_COMPENSATED). */
+wqa_status wqa_set_final_mode(wqa_ctx *ctx, wqa_final mode);
+
+/* Mass matrix (eq:Mass with the folded coefficient c).  c: device [N_1..N_d] of dtype
+ * on the all-mass grid; M: device [rows][S^d] of dtype (fully overwritten). */
+wqa_status wqa_assemble_mass(wqa_ctx *ctx, wqa_dtype dtype, const void *c, void *M,
+                             void *hip_stream);
+
+/* Stiffness matrix (eq:Stiffness with the folded diagonal coefficient).  a[dim]:
+ * device pointers, a[k] on the grid with the stiffness rule in direction k;
+ * K: device [rows][S^d] (fully overwritten). */
+wqa_status wqa_assemble_stiffness(wqa_ctx *ctx, wqa_dtype dtype, const void *const *a,
+                                  void *K, void *hip_stream);
+
+/* Both matrices in one pass over the rows (same arguments as the two calls above). */
+wqa_status wqa_assemble_fused(wqa_ctx *ctx, wqa_dtype dtype, const void *c,
+                              const void *const *a, void *M, void *K, void *hip_stream);
+
+/* Adjoint: with L = <gM, M> + <gK, K> (sums over every slot), writes dc = dL/dc and
+ * da[k] = dL/da_k at every grid point.  gM, gK: device [rows][S^d]; slots outside the
+ * space are ignored (may hold anything).  gM == NULL skips dc (dc must be NULL then);
+ * gK == NULL skips da (da must be NULL then).  Each grid point belongs to exactly
+ * one row, so every output element is written once, without atomics. */
+wqa_status wqa_assemble_adjoint(wqa_ctx *ctx, wqa_dtype dtype, const void *gM,
+                                const void *gK, void *dc, void *const *da,
+                                void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WQA_H */

@@ -163,7 +163,7 @@ static void decode(int code, int base, int d, int *digits)
 static int ipow(int b, int e) { int r = 1; while (e-- > 0) r *= b; return r; }
 
 /*
- * Forward assembly of the listed rows.
+ * Forward assembly of the listed rows (the exported entry points follow).
  *   xM[k], wM[k]: mass-rule nodes and weights of direction k, [n_k * Q] each.
  *   xK[k], wK[k]: stiffness-rule nodes and weights (only read when K_out != NULL).
  *   c: mass coefficient on the all-mass grid (read when M_out != NULL).
@@ -172,12 +172,12 @@ static int ipow(int b, int e) { int r = 1; while (e-- > 0) r *= b; return r; }
  *   M_out, K_out: [n_list][S^d] (either may be NULL).
  * Returns 0, or -1 for bad arguments, -2 when out of memory.
  */
-int oracle_assemble(int d, int p, const int64_t *n_el,
-                    const double *const *xM, const double *const *wM,
-                    const double *const *xK, const double *const *wK,
-                    const double *c, const double *const *a,
-                    const int64_t *rows, int64_t n_list,
-                    double *M_out, double *K_out)
+static int assemble_impl(int d, int p, const int64_t *n_el,
+                         const double *const *xM, const double *const *wM,
+                         const double *const *xK, const double *const *wK,
+                         const double *c, const double *const *a, int per_row,
+                         const int64_t *rows, int64_t n_list,
+                         double *M_out, double *K_out)
 {
     space_t sp;
     int rc = space_init(&sp, d, p, n_el);
@@ -209,7 +209,7 @@ int oracle_assemble(int d, int p, const int64_t *n_el,
                     for (int qc = 0; qc < QD; ++qc) {
                         int q[MAXD];
                         decode(qc, sp.Q, d, q);
-                        double prod = c[grid_offset(&sp, idx, q)];
+                        double prod = c[per_row ? r * QD + qc : grid_offset(&sp, idx, q)];
                         for (int k = 0; k < d; ++k) prod *= fM[k][q[k]][s[k]];
                         acc += prod;
                     }
@@ -223,7 +223,7 @@ int oracle_assemble(int d, int p, const int64_t *n_el,
                         for (int qc = 0; qc < QD; ++qc) {
                             int q[MAXD];
                             decode(qc, sp.Q, d, q);
-                            double prod = a[kk][grid_offset(&sp, idx, q)];
+                            double prod = a[kk][per_row ? r * QD + qc : grid_offset(&sp, idx, q)];
                             for (int k = 0; k < d; ++k)
                                 prod *= (k == kk) ? fK[k][q[k]][s[k]] : fM[k][q[k]][s[k]];
                             acc += prod;
@@ -236,6 +236,30 @@ int oracle_assemble(int d, int p, const int64_t *n_el,
     }
     space_free(&sp);
     return bad ? -1 : 0;
+}
+
+int oracle_assemble(int d, int p, const int64_t *n_el,
+                    const double *const *xM, const double *const *wM,
+                    const double *const *xK, const double *const *wK,
+                    const double *c, const double *const *a,
+                    const int64_t *rows, int64_t n_list,
+                    double *M_out, double *K_out)
+{
+    return assemble_impl(d, p, n_el, xM, wM, xK, wK, c, a, 0, rows, n_list, M_out, K_out);
+}
+
+/* Same as oracle_assemble, but the coefficients come per listed row: c[r][q] and
+ * a[k][r][q] hold the samples at the Q^d points of row rows[r] (q in C order), so
+ * a few rows of a very large space need no full grid on the host. */
+int oracle_assemble_rows(int d, int p, const int64_t *n_el,
+                         const double *const *xM, const double *const *wM,
+                         const double *const *xK, const double *const *wK,
+                         const double *c, const double *const *a,
+                         const int64_t *rows, int64_t n_list,
+                         double *M_out, double *K_out)
+{
+    if (!rows) return -1;
+    return assemble_impl(d, p, n_el, xM, wM, xK, wK, c, a, 1, rows, n_list, M_out, K_out);
 }
 
 /*

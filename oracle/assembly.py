@@ -47,6 +47,8 @@ def _lib():
                                     P(ctypes.c_int64), ctypes.c_int64,
                                     P(ctypes.c_double), P(ctypes.c_double)]
     lib.oracle_assemble.restype = ctypes.c_int
+    lib.oracle_assemble_rows.argtypes = lib.oracle_assemble.argtypes
+    lib.oracle_assemble_rows.restype = ctypes.c_int
     lib.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_int64),
                                    dpp, dpp, dpp, dpp,
                                    P(ctypes.c_int64), ctypes.c_int64,
@@ -100,9 +102,14 @@ def _f64(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
 
 
-def assemble(p, n_el, tables, c=None, a=None, rows=None):
-    """Rows of M (if c is given) and K (if a is given) as float64 [n_list, (2p+1)^d]."""
+def assemble(p, n_el, tables, c=None, a=None, rows=None, per_row=False):
+    """Rows of M (if c is given) and K (if a is given) as float64 [n_list, (2p+1)^d].
+
+    c and a[k] are full grids, or with per_row=True the samples of the listed rows only,
+    [n_list, (p+1)^d] in the point order of ``row_points``."""
     d = len(n_el)
+    if per_row and rows is None:
+        raise ValueError("per_row needs rows")
     lib = _lib()
     ne = np.ascontiguousarray(np.array(n_el, dtype=np.int64))
     n_rows = int(np.prod([n + p for n in n_el]))
@@ -118,7 +125,8 @@ def assemble(p, n_el, tables, c=None, a=None, rows=None):
     xK, wK = _ptr_array(tables["xK"]), _ptr_array(tables["wK"])
     keep += [xM, wM, xK, wK]
     P = ctypes.POINTER(ctypes.c_double)
-    rc = lib.oracle_assemble(
+    fn = lib.oracle_assemble_rows if per_row else lib.oracle_assemble
+    rc = fn(
         d, p, ne.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), xM, wM, xK, wK,
         None if c64 is None else c64.ctypes.data_as(P),
         None if a64 is None else _ptr_array(a64),
@@ -181,3 +189,24 @@ def row_points(p, n_el, rows):
     for k in range(d):
         off = off * N[k] + (idx[k][:, None] * Q + qs[None, :, k])
     return off
+
+
+def row_point_coords(p, n_el, tables, rows, field):
+    """Coordinates [n_list, (p+1)^d, d] of the points of the listed rows on the grid of
+    ``field`` ('c' or a direction k), in the point order of ``row_points``."""
+    d = len(n_el)
+    Q = p + 1
+    n = [ne + p for ne in n_el]
+    rows = np.asarray(rows, dtype=np.int64)
+    axes = grid_axes(tables, field)
+    idx = []
+    rem = rows.copy()
+    for k in reversed(range(d)):
+        idx.append(rem % n[k])
+        rem //= n[k]
+    idx = idx[::-1]
+    qs = np.array(np.unravel_index(np.arange(Q ** d), [Q] * d)).T
+    out = np.empty((rows.size, Q ** d, d))
+    for k in range(d):
+        out[:, :, k] = axes[k][idx[k][:, None] * Q + qs[None, :, k]]
+    return out

@@ -1,0 +1,38 @@
+// Internal interface between the host library (wqa_host.cpp) and the HIP kernels
+// (wqa_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wqa {
+
+constexpr int kMaxDim = 3;
+
+enum What { kWhatM = 1, kWhatK = 2, kWhatMK = 3 };
+
+// Sizes of the tensor-product space as the kernels see them.
+struct DevSpace {
+    int d, p;
+    int64_t n[kMaxDim];   // basis functions per direction
+    int64_t N[kMaxDim];   // grid points per direction (n * (p + 1))
+};
+
+// Contraction tables T[kind][dir] laid out [n_dir][Q][S] on the device, in the call's
+// dtype, plus FP64 copies for the FP64-accumulated final pass.
+struct DevTabs {
+    const void *t[2][kMaxDim];
+    const double *t64[2][kMaxDim];
+};
+
+// Forward assembly (mass, stiffness or both).  dtype 0 = FP32, 1 = FP64.
+hipError_t launch_forward(int dtype, int final_mode, int what, const DevSpace &sp,
+                          const DevTabs &tb, const void *c, const void *const *a,
+                          void *M, void *K, hipStream_t stream);
+
+// Adjoint (either or both upstream gradients).
+hipError_t launch_adjoint(int dtype, int final_mode, int what, const DevSpace &sp,
+                          const DevTabs &tb, const void *gM, const void *gK,
+                          void *dc, void *const *da, hipStream_t stream);
+
+}  // namespace wqa

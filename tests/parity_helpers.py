@@ -1,0 +1,94 @@
+"""Input recipes for the parity tests, evaluated separately for each side at that
+side's own rule nodes (the library's nodes for the device run, the oracle's nodes for
+the oracle), plus the error metrics of the comparisons.
+
+recipe:
+  ("random", seed)      i.i.d. U(0.5, 1.5) samples on the grid -- one host array, the
+                        same values go to both sides (node positions do not matter)
+  ("config1",)          c = 1 + 0.5 sin(2 pi x) sin(2 pi y), a_k = 1
+  ("fourier", config)   random Fourier fields of that config (field 0 = c, k+1 = a_k)
+  ("deformed",)         deformed-cube coefficients (det J, det J / J_kk^2)
+"""
+import numpy as np
+import torch
+
+import structured as st
+import synth_inputs as si
+from oracle import assembly as oa
+
+
+def grid_shape(p, n_el):
+    return tuple((e + p) * (p + 1) for e in n_el)
+
+
+def _random_fields(p, n_el, seed):
+    rng = np.random.default_rng(seed)
+    shape = grid_shape(p, n_el)
+    return [rng.uniform(0.5, 1.5, size=shape) for _ in range(len(n_el) + 1)]
+
+
+def device_fields(space, recipe, dtype):
+    """[c, a_1..a_d] as device tensors of dtype, sampled at the library's nodes."""
+    p, n_el, d = space.degree, space.n_elem, space.dim
+    dev = space.device
+    kind = recipe[0]
+    if kind == "random":
+        return [torch.from_numpy(f).to(dev, dtype) for f in _random_fields(p, n_el, recipe[1])]
+    out = []
+    for field in ["c"] + list(range(d)):
+        axes = space.grid_axes(field)
+        if kind == "config1":
+            if field == "c":
+                x = torch.tensor(axes[0], dtype=torch.float64, device=dev)[:, None]
+                y = torch.tensor(axes[1], dtype=torch.float64, device=dev)[None, :]
+                out.append(si.config1_c(x, y).to(dtype).contiguous())
+            else:
+                out.append(torch.ones(space.grid_shape, dtype=dtype, device=dev))
+        elif kind == "fourier":
+            fid = 0 if field == "c" else field + 1
+            out.append(si.fourier_grid(axes, si.fourier_modes(recipe[1], fid, d), dtype, dev).contiguous())
+        elif kind == "deformed":
+            out.append(si.deformed_cube_grid(axes, field, dtype, dev).contiguous())
+        else:
+            raise ValueError(recipe)
+    return out
+
+
+def oracle_row_fields(tabs, p, n_el, rows, recipe):
+    """[c, a_1..a_d] samples of the listed rows, [n_list, (p+1)^d] float64, at the
+    oracle's nodes (random recipe: gathered from the shared host array)."""
+    d = len(n_el)
+    kind = recipe[0]
+    n = [e + p for e in n_el]
+    if kind == "random":
+        pts = st.point_offsets(n, p, rows)
+        return [f.reshape(-1)[pts] for f in _random_fields(p, n_el, recipe[1])]
+    out = []
+    for field in ["c"] + list(range(d)):
+        xyz = oa.row_point_coords(p, n_el, tabs, rows, field)          # [n_list, QD, d]
+        flat = xyz.reshape(-1, d)
+        if kind == "config1":
+            v = si.config1_c(flat[:, 0], flat[:, 1]) if field == "c" else np.ones(len(flat))
+        elif kind == "fourier":
+            fid = 0 if field == "c" else field + 1
+            v = si.fourier_points(flat, si.fourier_modes(recipe[1], fid, d))
+        elif kind == "deformed":
+            v = si.deformed_cube_points(flat, field)
+        else:
+            raise ValueError(recipe)
+        out.append(v.reshape(xyz.shape[:2]))
+    return out
+
+
+def oracle_forward(p, n_el, rows, recipe, want_m=True, want_k=True):
+    tabs = oa.rule_tables(p, n_el)
+    f = oracle_row_fields(tabs, p, n_el, rows, recipe)
+    M, K = oa.assemble(p, n_el, tabs, c=f[0] if want_m else None, a=f[1:] if want_k else None,
+                       rows=rows, per_row=True)
+    return M, K
+
+
+def normwise_error(got, want):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    return float(np.abs(got - want).max() / max(np.abs(want).max(), 1e-300))

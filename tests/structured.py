@@ -67,3 +67,40 @@ def entry_relative_error(got, want, floor=0.0):
     if not m.any():
         return 0.0
     return float((np.abs(got[m] - want[m]) / np.abs(want[m])).max())
+
+
+def point_offsets(n, p, rows):
+    """[len(rows), (p+1)^d] flat grid offsets of the points owned by each row: row i owns
+    grid point (i_k (p+1) + q_k)_k of the C-ordered [n_k (p+1)] grid, q in C order."""
+    d = len(n)
+    Q = p + 1
+    idx = row_multi(n, rows)
+    qs = np.array(np.unravel_index(np.arange(Q ** d), [Q] * d))       # [d, QD]
+    off = np.zeros((len(idx[0]), Q ** d), dtype=np.int64)
+    for k in range(d):
+        off = off * (n[k] * Q) + (idx[k][:, None] * Q + qs[k][None, :])
+    return off
+
+
+def sample_rows(n, p, count, seed):
+    """Deterministic row sample that covers every boundary class: rows whose index in
+    each direction is drawn from the first and last 2p+1 indices and a few interior
+    ones, plus uniformly random rows; sorted, unique."""
+    rng = np.random.default_rng(seed)
+    d = len(n)
+    cand = []
+    for nk in n:
+        edge = list(range(min(nk, 2 * p + 1))) + list(range(max(0, nk - 2 * p - 1), nk))
+        inner = list(rng.integers(0, nk, size=4))
+        cand.append(np.unique(np.array(edge + inner)))
+    picks = np.stack([rng.choice(c, size=count) for c in cand])           # [d, count]
+    flat = np.zeros(count, dtype=np.int64)
+    for k in range(d):
+        flat = flat * n[k] + picks[k]
+    corners = np.array(np.meshgrid(*[[0, nk - 1] for nk in n], indexing="ij")).reshape(d, -1)
+    cflat = np.zeros(corners.shape[1], dtype=np.int64)
+    for k in range(d):
+        cflat = cflat * n[k] + corners[k]
+    total = int(np.prod(n))
+    rand = rng.integers(0, total, size=count // 2)
+    return np.unique(np.concatenate([flat, cflat, rand]))

@@ -1,0 +1,265 @@
+"""GPU parity: libwqa's HIP kernels against the FP64 oracle (runs on an MI355X).
+
+Forward and adjoint, every dimension/degree/dtype/final-pass mode on small spaces whose
+last direction spans several wave tiles with a ragged tail (full comparison of every
+row), and the benchmark workloads at full size on a row sample that covers every
+boundary class.  Bars: FP64 within 1e-12, FP32 within 1e-5, row-scaled relative error
+(the largest error in a row over the largest exact entry of that row); gradients
+normwise per field.
+"""
+import numpy as np
+import pytest
+import torch
+
+import parity_helpers as ph
+import structured as st
+import synth_inputs as si
+from oracle import assembly as oa
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def wqa():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_1710_01048_amd as mod
+    return mod
+
+
+def _rows_all(space):
+    return np.arange(space.n_rows)
+
+
+SMALL = [
+    (2, 2, (3, 4)), (2, 2, (5, 21)), (2, 3, (4, 4)), (2, 3, (7, 23)),
+    (3, 2, (3, 4, 5)), (3, 2, (4, 3, 21)), (3, 3, (4, 4, 4)), (3, 3, (5, 4, 13)),
+    (3, 3, (6, 7, 23)),
+]
+
+
+def _ids(v):
+    return "d%d-p%d-%s" % (v[0], v[1], "x".join(map(str, v[2])))
+
+
+@pytest.mark.parametrize("case", SMALL, ids=_ids)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("what", ["mass", "stiffness", "fused"])
+def test_forward_small_every_row(wqa, case, dtype, what):
+    d, p, n_el = case
+    sp = wqa.Space(d, p, n_el)
+    recipe = ("random", 100 + d * 10 + p)
+    f = ph.device_fields(sp, recipe, dtype)
+    rows = _rows_all(sp)
+    Mw, Kw = ph.oracle_forward(p, n_el, rows, recipe)
+    nan = float("nan")
+    M = torch.full((sp.n_rows, sp.slots_per_row), nan, dtype=dtype, device=sp.device)
+    K = torch.full_like(M, nan)
+    if what == "mass":
+        sp.assemble_mass(f[0], M)
+    elif what == "stiffness":
+        sp.assemble_stiffness(f[1:], K)
+    else:
+        sp.assemble_fused(f[0], f[1:], M, K)
+    torch.cuda.synchronize()
+    if what in ("mass", "fused"):
+        Mh = M.cpu().numpy()
+        assert not np.isnan(Mh).any(), "unwritten slots in M"
+        assert st.row_scaled_error(Mh, Mw) <= TOL[dtype]
+        assert np.all(Mh[Mw == 0] == 0)
+    if what in ("stiffness", "fused"):
+        Kh = K.cpu().numpy()
+        assert not np.isnan(Kh).any(), "unwritten slots in K"
+        assert st.row_scaled_error(Kh, Kw) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["plain", "compensated", "f64acc"])
+@pytest.mark.parametrize("case", [(3, 3, (5, 4, 13)), (2, 2, (5, 21))], ids=_ids)
+def test_forward_final_modes_fp32(wqa, case, mode):
+    d, p, n_el = case
+    sp = wqa.Space(d, p, n_el)
+    sp.set_final_mode(mode)
+    recipe = ("random", 7)
+    f = ph.device_fields(sp, recipe, torch.float32)
+    M, K = sp.assemble_fused(f[0], f[1:])
+    Mw, Kw = ph.oracle_forward(p, n_el, _rows_all(sp), recipe)
+    assert st.row_scaled_error(M.cpu().numpy(), Mw) <= 1e-5
+    assert st.row_scaled_error(K.cpu().numpy(), Kw) <= 1e-5
+
+
+@pytest.mark.parametrize("case", SMALL, ids=_ids)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("what", ["mass", "stiffness", "both"])
+def test_adjoint_small_every_point(wqa, case, dtype, what):
+    d, p, n_el = case
+    sp = wqa.Space(d, p, n_el)
+    n = list(sp.n_basis)
+    rng = np.random.default_rng(31 + d + p)
+    valid = si.slot_valid_mask(n_el, p).numpy()
+    # garbage in invalid slots must be ignored
+    gM = np.where(valid, rng.normal(size=valid.shape), 1e30)
+    gK = np.where(valid, rng.normal(size=valid.shape), -1e30)
+    use_m, use_k = what in ("mass", "both"), what in ("stiffness", "both")
+    dc, da = sp.adjoint(torch.from_numpy(gM).to(sp.device, dtype) if use_m else None,
+                        torch.from_numpy(gK).to(sp.device, dtype) if use_k else None)
+    torch.cuda.synchronize()
+    tabs = oa.rule_tables(p, n_el)
+    rows = _rows_all(sp)
+    wc, wa = oa.adjoint(p, n_el, tabs, np.where(valid, gM, 0) if use_m else None,
+                        np.where(valid, gK, 0) if use_k else None, rows=rows)
+    pts = st.point_offsets(n, p, rows)
+    if use_m:
+        got = dc.reshape(-1).cpu().numpy()[pts]
+        assert ph.normwise_error(got, wc) <= TOL[dtype]
+    if use_k:
+        for k in range(d):
+            got = da[k].reshape(-1).cpu().numpy()[pts]
+            assert ph.normwise_error(got, wa[k]) <= TOL[dtype], k
+
+
+def test_config1_mass_2d_quadratic(wqa):
+    # 2D C^1 quadratic, 32 x 32 elements, c = 1 + 0.5 sin sin, FP64 mass (every row)
+    sp = wqa.Space(2, 2, (32, 32))
+    recipe = ("config1",)
+    f = ph.device_fields(sp, recipe, torch.float64)
+    M = sp.assemble_mass(f[0])
+    Mw, _ = ph.oracle_forward(2, (32, 32), _rows_all(sp), recipe, want_k=False)
+    Mh = M.cpu().numpy()
+    assert sp.n_rows == 1156 and sp.slots_per_row == 25
+    assert st.row_scaled_error(Mh, Mw) <= 1e-12
+    assert st.entry_relative_error(Mh, Mw) <= 1e-12
+
+
+def _sampled_forward(wqa, d, p, n_el, recipe, dtype, mode=None, count=300):
+    sp = wqa.Space(d, p, n_el)
+    if mode is not None:
+        sp.set_final_mode(mode)
+    f = ph.device_fields(sp, recipe, dtype)
+    M, K = sp.assemble_fused(f[0], f[1:])
+    rows = st.sample_rows(list(sp.n_basis), p, count, seed=hash(n_el) % 1000)
+    ridx = torch.from_numpy(rows).to(sp.device)
+    Mg, Kg = M[ridx].cpu().numpy(), K[ridx].cpu().numpy()
+    del M, K, f
+    Mw, Kw = ph.oracle_forward(p, n_el, rows, recipe)
+    return st.row_scaled_error(Mg, Mw), st.row_scaled_error(Kg, Kw), st.entry_relative_error(Mg, Mw)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_config2_fused_3d_quadratic(wqa, dtype):
+    eM, eK, eMe = _sampled_forward(wqa, 3, 2, (64, 64, 64), ("fourier", 2), dtype)
+    print(f"config2 {dtype}: row-scaled M {eM:.3e} K {eK:.3e}; entrywise M {eMe:.3e}")
+    assert eM <= TOL[dtype] and eK <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype,mode", [(torch.float64, None), (torch.float32, 1),
+                                        (torch.float32, 0), (torch.float32, 2)],
+                         ids=["f64", "f32-compensated", "f32-plain", "f32-f64acc"])
+def test_config3_fused_3d_cubic_deformed(wqa, dtype, mode):
+    eM, eK, eMe = _sampled_forward(wqa, 3, 3, (96, 96, 96), ("deformed",), dtype, mode)
+    print(f"config3 {dtype} mode {mode}: row-scaled M {eM:.3e} K {eK:.3e}; entrywise M {eMe:.3e}")
+    assert eM <= TOL[dtype] and eK <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_config4_adjoint_3d_cubic(wqa, dtype):
+    # 64^3 cubic, Fourier coefficients, G ~ N(0,1) (seeds 4001, 4002), gradients through
+    # the autograd Function, sampled rows against the oracle's adjoint
+    p, n_el = 3, (64, 64, 64)
+    sp = wqa.Space(3, p, n_el)
+    f = [x.requires_grad_(True) for x in ph.device_fields(sp, ("fourier", 4), dtype)]
+    M, K = wqa.WQAssemble.apply(sp, *f)
+    gM = si.upstream_gradient(n_el, p, 4001, dtype, sp.device)
+    gK = si.upstream_gradient(n_el, p, 4002, dtype, sp.device)
+    torch.autograd.backward([M, K], [gM, gK])
+    rows = st.sample_rows(list(sp.n_basis), p, 200, seed=4)
+    ridx = torch.from_numpy(rows).to(sp.device)
+    pts = st.point_offsets(list(sp.n_basis), p, rows)
+    tabs = oa.rule_tables(p, n_el)
+    wc, wa = oa.adjoint(p, n_el, tabs, gM[ridx].double().cpu().numpy(), gK[ridx].double().cpu().numpy(),
+                        rows=rows)
+    errs = [ph.normwise_error(f[0].grad.reshape(-1).cpu().numpy()[pts], wc)]
+    errs += [ph.normwise_error(f[k + 1].grad.reshape(-1).cpu().numpy()[pts], wa[k]) for k in range(3)]
+    print(f"config4 {dtype}: normwise gradient errors {['%.3e' % e for e in errs]}")
+    assert max(errs) <= TOL[dtype]
+
+
+def test_config4_central_differences(wqa):
+    # dL/dtheta at 64 seeded quadrature points (16 per field) against central
+    # differences h = 1e-6 in FP64 of L = <G_M, M> + <G_K, K>, evaluated by the oracle
+    # on the one row that owns the point; points whose rule weight is 0 are skipped
+    p, n_el = 3, (64, 64, 64)
+    sp = wqa.Space(3, p, n_el)
+    recipe = ("fourier", 4)
+    f = ph.device_fields(sp, recipe, torch.float64)
+    gM = si.upstream_gradient(n_el, p, 4001, torch.float64, sp.device)
+    gK = si.upstream_gradient(n_el, p, 4002, torch.float64, sp.device)
+    dc, da = sp.adjoint(gM, gK)
+    grads = [dc] + list(da)
+    tabs = oa.rule_tables(p, n_el)
+    n = list(sp.n_basis)
+    rng = np.random.default_rng(4064)
+    Q = p + 1
+    checked = 0
+    h = 1e-6
+    while checked < 64:
+        field = checked // 16
+        row = int(rng.integers(0, sp.n_rows))
+        q = int(rng.integers(0, Q ** 3))
+        qs = np.unravel_index(q, (Q, Q, Q))
+        idx = st.row_multi(n, [row])
+        # skip zero-weight (padding) points of the rule that field uses
+        zero = False
+        for k in range(3):
+            key = "wK" if (field >= 1 and k == field - 1) else "wM"
+            if tabs[key][k][idx[k][0] * Q + qs[k]] == 0.0:
+                zero = True
+        if zero:
+            continue
+        vals = ph.oracle_row_fields(tabs, p, n_el, np.array([row]), recipe)
+        gm = gM[row].cpu().numpy()[None]
+        gk = gK[row].cpu().numpy()[None]
+        Ls = []
+        for sign in (1, -1):
+            v = [x.copy() for x in vals]
+            v[field][0, q] += sign * h
+            Mr, Kr = oa.assemble(p, n_el, tabs, c=v[0], a=v[1:], rows=[row], per_row=True)
+            Ls.append((gm * Mr).sum() + (gk * Kr).sum())
+        fd = (Ls[0] - Ls[1]) / (2 * h)
+        off = st.point_offsets(n, p, [row])[0, q]
+        got = float(grads[field].reshape(-1)[off])
+        # rounding bound of the difference quotient for this row
+        Mr, Kr = oa.assemble(p, n_el, tabs, c=vals[0], a=vals[1:], rows=[row], per_row=True)
+        bound = 4e-16 * ((np.abs(gm * Mr)).sum() + (np.abs(gk * Kr)).sum()) / h
+        assert abs(fd - got) <= 10 * bound + 1e-9 * abs(got), (field, row, q, fd, got, bound)
+        checked += 1
+
+
+def test_deterministic_and_stream_ordered(wqa):
+    sp = wqa.Space(3, 3, (8, 9, 10))
+    f = ph.device_fields(sp, ("random", 5), torch.float32)
+    M1, K1 = sp.assemble_fused(f[0], f[1:])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        M2, K2 = sp.assemble_fused(f[0], f[1:])
+    s.synchronize()
+    assert torch.equal(M1, M2) and torch.equal(K1, K2)
+
+
+def test_autograd_gradcheck_tiny(wqa):
+    sp = wqa.Space(2, 2, (3, 4))
+    rng = np.random.default_rng(2)
+    f = [torch.tensor(rng.uniform(0.5, 1.5, sp.grid_shape), device=sp.device, requires_grad=True)
+         for _ in range(3)]
+    assert torch.autograd.gradcheck(lambda *x: wqa.WQAssemble.apply(sp, *x), f, eps=1e-6, atol=1e-9,
+                                    rtol=1e-7, fast_mode=True)
+
+
+def test_errors_surface(wqa):
+    sp = wqa.Space(3, 2, (3, 3, 3))
+    c = torch.ones(sp.grid_shape, device=sp.device)
+    with pytest.raises(ValueError):
+        sp.assemble_mass(c.double(), M=torch.empty(3, device=sp.device))
+    with pytest.raises(wqa.WQAError):
+        sp.set_final_mode(7)
