@@ -30,6 +30,7 @@ import synth_inputs as si  # noqa: E402
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 P, NEL = 3, (160, 160, 160)
 CONFIG_ID = 5
+FINAL_MODE = 1                 # compensated final pass (wqa.FINAL_COMPENSATED)
 METRIC = "assembled nnz/s (3D C2 cubic M+K) FP32 vs FP64 at stated err; adjoint nnz/s"
 
 
@@ -159,7 +160,7 @@ def main():
     assert torch.cuda.is_available(), "needs a HIP device"
     dev = torch.device("cuda:0")
     sp = wqa.Space(3, P, NEL, device=dev)
-    sp.set_final_mode(wqa.FINAL_COMPENSATED)
+    sp.set_final_mode(FINAL_MODE)
     nnz_mat = sp.n_rows * sp.slots_per_row
     nnz_step = 4 * nnz_mat
     log(f"space: {sp.n_rows} rows x {sp.slots_per_row} slots, grid {sp.grid_shape}")
@@ -171,6 +172,24 @@ def main():
     fwd32, adj32 = float(np.mean(r32["fwd_ms"])), float(np.mean(r32["adj_ms"]))
     step_ms = r32["wall_s"] * 1e3 / args.steps
     log(f"fp32: forward {fwd32:.3f} ms, adjoint {adj32:.3f} ms, step {step_ms:.3f} ms")
+
+    # forward time of each FP32 final-pass mode (same inputs and outputs)
+    mode_ms = {}
+    M, K = r32["out"][0], r32["out"][1]
+    for name, mode in (("plain", wqa.FINAL_PLAIN), ("compensated", wqa.FINAL_COMPENSATED),
+                       ("f64_accumulate", wqa.FINAL_F64)):
+        sp.set_final_mode(mode)
+        sp.assemble_fused(fields[0], fields[1:], M, K)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        for i in range(5):
+            evs[i].record()
+            sp.assemble_fused(fields[0], fields[1:], M, K)
+        evs[5].record()
+        torch.cuda.synchronize()
+        mode_ms[name] = evs[0].elapsed_time(evs[5]) / 5
+    sp.set_final_mode(FINAL_MODE)
+    sp.assemble_fused(fields[0], fields[1:], M, K)   # leave the headline mode's results in M, K
+    log(f"fp32 forward by final pass: {mode_ms}")
 
     b = 4  # bytes per FP32 value
     fwd_bytes = sp.n_rows * (2 * sp.slots_per_row + 4 * sp.points_per_row) * b
@@ -211,6 +230,7 @@ def main():
                    "rows": sp.n_rows, "slots_per_row": sp.slots_per_row, "nnz_per_step": nnz_step,
                    "parallelism": "single GPU"},
         "forward_ms": fwd32,
+        "forward_ms_by_final_pass": mode_ms,
         "adjoint_ms": adj32,
         "assembled_nnz_per_s_fp32": 2 * nnz_mat / (fwd32 * 1e-3),
         "adjoint_nnz_per_s_fp32": 2 * nnz_mat / (adj32 * 1e-3),

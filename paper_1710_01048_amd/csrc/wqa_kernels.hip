@@ -69,365 +69,534 @@ struct Acc<float, 2> {
 template <typename T, int FINAL> struct FinalTab { using type = T; };
 template <> struct FinalTab<float, 2> { using type = double; };
 
+// Table rows of the leading directions are the same for the whole wave; reading them
+// through the constant address space lets them live in scalar registers even after the
+// kernel has stored results (the tables are never written by a kernel).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> table(const DevTabs &tb, int kind, int dir) {
+    return (cptr<T>)(const T *)tb.t[kind][dir];
+}
+
 template <typename T, int FINAL>
-__device__ __forceinline__ const typename FinalTab<T, FINAL>::type *final_table(const DevTabs &tb, int kind, int dir) {
-    if constexpr (FINAL == 2 && sizeof(T) == 4) return tb.t64[kind][dir];
-    else return (const T *)tb.t[kind][dir];
+__device__ __forceinline__ cptr<typename FinalTab<T, FINAL>::type> final_table(const DevTabs &tb, int kind, int dir) {
+    if constexpr (FINAL == 2 && sizeof(T) == 4) return (cptr<double>)tb.t64[kind][dir];
+    else return (cptr<T>)(const T *)tb.t[kind][dir];
+}
+
+__device__ __forceinline__ void phase_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Forces the values of a register array to be computed before this point (an empty asm
+// that "modifies" them), so that later phases cannot delay the arithmetic that
+// consumes the earlier phase's loads.
+template <typename T, int A, int B>
+__device__ __forceinline__ void pin(T (&V)[A][B]) {
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+#pragma unroll
+        for (int b = 0; b < B; ++b) asm volatile("" : "+v"(V[a][b]));
+}
+
+template <typename T, int A, int B, int C>
+__device__ __forceinline__ void pin(T (&V)[A][B][C]) {
+#pragma unroll
+    for (int a = 0; a < A; ++a) pin(V[a]);
+}
+
+// Rows whose nodes sit one per element of their support (every row but the p at each
+// end of a direction) have tables that vanish outside q <= s <= q + P: node q only
+// meets the P+1 functions living on its element.  The banded code paths skip those
+// zeros; the others run the full Q x S loops.  Both give bitwise the same sums.
+template <int P>
+__device__ __forceinline__ constexpr bool in_band(int q, int s) {
+    return s >= q && s <= q + P;
+}
+
+// Q consecutive samples starting at p (16-byte aligned when Q * sizeof(T) is a
+// multiple of 16: row points start at multiples of Q in a 16-byte aligned grid).
+template <typename T, int Q>
+__device__ __forceinline__ void load_q(const T *__restrict__ p, T (&v)[Q]) {
+    if constexpr (sizeof(T) == 4 && Q == 4) {
+        const float4 x = *reinterpret_cast<const float4 *>(p);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    } else if constexpr (sizeof(T) == 8 && Q == 4) {
+        const double2 x = *reinterpret_cast<const double2 *>(p);
+        const double2 y = *reinterpret_cast<const double2 *>(p + 2);
+        v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = p[q];
+    }
+}
+
+// Per-wave tile context shared by the forward and adjoint bodies.
+struct Tile {
+    int64_t i1, i2, t0, row0, il, nl;
+    int rows_here, r;
+    bool in_tile, active;
+};
+
+template <int D>
+__device__ __forceinline__ Tile make_tile(const DevSpace &sp, int64_t task, int tiles_per_line, int R,
+                                          int lanes_per_row, int lane) {
+    Tile t;
+    const int64_t line = task / tiles_per_line;
+    const int tile = (int)(task - line * tiles_per_line);
+    t.nl = sp.n[D - 1];
+    if constexpr (D == 3) {
+        t.i1 = line / sp.n[1];
+        t.i2 = line - t.i1 * sp.n[1];
+    } else {
+        t.i1 = line;
+        t.i2 = 0;
+    }
+    t.t0 = (int64_t)tile * R;
+    t.rows_here = (int)((t.nl - t.t0) < R ? (t.nl - t.t0) : R);
+    t.r = lane / lanes_per_row;
+    t.in_tile = t.r < R;
+    t.active = t.r < t.rows_here;
+    t.il = t.t0 + (t.active ? t.r : 0);
+    t.row0 = line * t.nl + t.t0;
+    return t;
+}
+
+template <int D, int P>
+__device__ __forceinline__ bool tile_banded(const DevSpace &sp, const Tile &t) {
+    bool b = t.i1 >= P && t.i1 < sp.n[0] - P;
+    if constexpr (D == 3) b = b && t.i2 >= P && t.i2 < sp.n[1] - P;
+    return b;
 }
 
 // --------------------------------------------------------------------------------------
+// Forward.  Lane (r, s_d): row r of the tile, slot column s_d of the last direction.
+template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R>
+struct Forward {
+    static constexpr int Q = P + 1, S = 2 * P + 1;
+    static constexpr int SL = (D == 3) ? S * S : S;
+    static constexpr int SD = S * SL;
+    using FT = typename FinalTab<T, FINAL>::type;
+
+    const DevSpace &sp;
+    const DevTabs &tb;
+    const Tile &t;
+    T *stage;          // R * SL values of this wave
+    int lane, sl;
+    int64_t base;      // grid offset of this row's point (0, .., 0)
+    int64_t N2, N3;
+
+    // V[s2][q1] = sum_{q2} sum_{q3} f[q1][q2][q3] t3[q3][sl] t2[q2][s2]     (d = 3)
+    // V[0][q1]  = sum_{q2} f[q1][q2] t2[q2][sl]                            (d = 2)
+    __device__ __forceinline__ void contract(const T *__restrict__ f, const T *t_last, cptr<T> t2,
+                                             T (&V)[S][Q], bool accumulate) const {
+        T tl[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) tl[q] = t_last[q * S + sl];
+        // wave-uniform part of the address, plus a 32-bit per-lane offset
+        const uint32_t lo = (uint32_t)(t.il * Q);
+        if constexpr (D == 3) {
+            const T *fb = f + ((t.i1 * Q) * N2 + t.i2 * Q) * N3;
+#pragma unroll
+            for (int q1 = 0; q1 < Q; ++q1) {
+                T U[Q];
+#pragma unroll
+                for (int q2 = 0; q2 < Q; ++q2) {
+                    T v[Q];
+                    load_q<T, Q>(fb + ((int64_t)q1 * N2 + q2) * N3 + lo, v);
+                    T acc = T(0);
+#pragma unroll
+                    for (int q3 = 0; q3 < Q; ++q3) acc = fma(v[q3], tl[q3], acc);
+                    U[q2] = acc;
+                }
+#pragma unroll
+                for (int s2 = 0; s2 < S; ++s2) {
+                    T acc = accumulate ? V[s2][q1] : T(0);
+#pragma unroll
+                    for (int q2 = 0; q2 < Q; ++q2)
+                        if (!BAND || in_band<P>(q2, s2)) acc = fma(U[q2], t2[q2 * S + s2], acc);
+                    V[s2][q1] = acc;
+                }
+            }
+        } else {
+            const T *fb = f + (t.i1 * Q) * N2;
+#pragma unroll
+            for (int q1 = 0; q1 < Q; ++q1) {
+                T v[Q];
+                load_q<T, Q>(fb + (int64_t)q1 * N2 + lo, v);
+                T acc = accumulate ? V[0][q1] : T(0);
+#pragma unroll
+                for (int q2 = 0; q2 < Q; ++q2) acc = fma(v[q2], tl[q2], acc);
+                V[0][q1] = acc;
+            }
+        }
+    }
+
+    // Final pass over q1 and store: X[s1][s2][sl] = sum_q1 fa[q1][s1] Va[s2][q1]
+    // (+ fb[q1][s1] Vb[s2][q1]), one s1 slab at a time through LDS.
+    template <bool TWO>
+    __device__ __forceinline__ void emit(cptr<FT> fa, const T (&Va)[S][Q], cptr<FT> fb, const T (&Vb)[S][Q],
+                                         T *__restrict__ out) const {
+        const bool ok_last = (t.il - P + sl >= 0) && (t.il - P + sl < t.nl);
+        constexpr int NS2 = (D == 3) ? S : 1;
+#pragma unroll
+        for (int s1 = 0; s1 < S; ++s1) {
+            const bool ok1 = (t.i1 - P + s1 >= 0) && (t.i1 - P + s1 < sp.n[0]);
+            if (t.in_tile) {
+#pragma unroll
+                for (int s2 = 0; s2 < NS2; ++s2) {
+                    bool ok = ok1 && ok_last;
+                    if constexpr (D == 3) ok = ok && (t.i2 - P + s2 >= 0) && (t.i2 - P + s2 < sp.n[1]);
+                    Acc<T, FINAL> acc;
+#pragma unroll
+                    for (int q1 = 0; q1 < Q; ++q1) {
+                        if (!BAND || in_band<P>(q1, s1)) {
+                            acc.add(fa[q1 * S + s1], Va[s2][q1]);
+                            if constexpr (TWO) acc.add(fb[q1 * S + s1], Vb[s2][q1]);
+                        }
+                    }
+                    stage[t.r * SL + s2 * S + sl] = ok ? acc.get() : T(0);
+                }
+            }
+            wave_lds_sync();
+            const int n_here = t.rows_here * SL;
+            T *ob = out + t.row0 * SD + s1 * SL;
+#pragma unroll 2
+            for (int e = lane; e < n_here; e += 64) {
+                const int rr = e / SL, tt = e - (e / SL) * SL;
+                ob[(uint32_t)(rr * SD + tt)] = stage[e];
+            }
+            wave_lds_sync();
+        }
+    }
+};
+
+template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R>
+__device__ __forceinline__ void forward_body(const DevSpace &sp, const DevTabs &tb, const Tile &t, T *stage,
+                                             int lane, const T *__restrict__ cf, const T *__restrict__ a0,
+                                             const T *__restrict__ a1, const T *__restrict__ a2,
+                                             T *__restrict__ Mo, T *__restrict__ Ko) {
+    using F = Forward<T, P, D, FINAL, BAND, WPB, R>;
+    constexpr int Q = F::Q, S = F::S;
+    using FT = typename F::FT;
+    F fw{sp, tb, t, stage, lane, lane - t.r * S, 0, sp.N[1], (D == 3) ? sp.N[2] : 1};
+    if constexpr (D == 3) fw.base = ((t.i1 * Q) * fw.N2 + t.i2 * Q) * fw.N3 + t.il * Q;
+    else fw.base = (t.i1 * Q) * fw.N2 + t.il * Q;
+    const int64_t rs = (int64_t)Q * S;
+    cptr<T> M2 = table<T>(tb, 0, 1) + (D == 3 ? t.i2 : 0) * rs;
+    cptr<T> K2 = table<T>(tb, 1, 1) + (D == 3 ? t.i2 : 0) * rs;
+    const T *ML = (const T *)tb.t[0][D - 1] + t.il * rs;
+    const T *KL = (const T *)tb.t[1][D - 1] + t.il * rs;
+    cptr<FT> fM1 = final_table<T, FINAL>(tb, 0, 0) + t.i1 * rs;
+    cptr<FT> fK1 = final_table<T, FINAL>(tb, 1, 0) + t.i1 * rs;
+    // The barriers keep each field's loads next to their use, so that the samples of
+    // only one field are live at a time (register pressure sets occupancy): the empty
+    // asm with a memory clobber stops loads from being hoisted across it, the
+    // scheduling barrier stops the machine scheduler from interleaving the phases.
+    if constexpr ((WHAT & kWhatM) != 0) {
+        T V[S][Q];
+        fw.contract(cf, ML, M2, V, false);
+        pin(V);
+        phase_barrier();
+        fw.template emit<false>(fM1, V, fM1, V, Mo);
+        phase_barrier();
+    }
+    if constexpr ((WHAT & kWhatK) != 0) {
+        T V1[S][Q], V2[S][Q];
+        if constexpr (D == 3) {
+            fw.contract(a0, ML, M2, V1, false);   // term 1: stiffness table in direction 1
+            pin(V1);
+            phase_barrier();
+            fw.contract(a1, ML, K2, V2, false);   // term 2: stiffness table in direction 2
+            pin(V2);
+            phase_barrier();
+            fw.contract(a2, KL, M2, V2, true);    // term 3: stiffness table in direction 3
+        } else {
+            fw.contract(a0, ML, M2, V1, false);       // term 1: stiffness table in direction 1
+            pin(V1);
+            phase_barrier();
+            fw.contract(a1, KL, M2, V2, false);       // term 2: stiffness table in direction 2
+        }
+        pin(V2);
+        phase_barrier();
+        fw.template emit<true>(fK1, V1, fM1, V2, Ko);
+    }
+}
+
 template <typename T, int P, int D, int WHAT, int FINAL, int WPB>
 __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     DevSpace sp, DevTabs tb, const T *__restrict__ cf, const T *__restrict__ a0,
     const T *__restrict__ a1, const T *__restrict__ a2, T *__restrict__ Mo,
     T *__restrict__ Ko, int64_t n_tasks, int tiles_per_line) {
-    constexpr int Q = P + 1, S = 2 * P + 1;
-    constexpr int R = 64 / S;                     // rows per wave tile
-    constexpr int SL = (D == 3) ? S * S : S;      // slots of one s_1 slab
-    constexpr int SD = S * SL;
-    constexpr bool DO_M = (WHAT & kWhatM) != 0, DO_K = (WHAT & kWhatK) != 0;
-    constexpr int NMAT = (DO_M ? 1 : 0) + (DO_K ? 1 : 0);
-    using FT = typename FinalTab<T, FINAL>::type;
-    __shared__ T stage[WPB][NMAT][R * SL];
-
-    const int wave = (int)(threadIdx.x >> 6);
+    constexpr int S = 2 * P + 1;
+    constexpr int R = 64 / S;                      // rows per wave tile
+    constexpr int SL = (D == 3) ? S * S : S;
+    __shared__ T stage[WPB][R * SL];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
     const int64_t task = (int64_t)blockIdx.x * WPB + wave;
-    if (task >= n_tasks) return;                  // whole wave leaves; no block barriers below
-    const int64_t line = task / tiles_per_line;
-    const int tile = (int)(task - line * tiles_per_line);
-    const int64_t nl = sp.n[D - 1];
-    int64_t i1, i2 = 0;
-    if constexpr (D == 3) {
-        i1 = line / sp.n[1];
-        i2 = line - i1 * sp.n[1];
-    } else {
-        i1 = line;
-    }
-    const int64_t t0 = (int64_t)tile * R;
-    const int rows_here = (int)((nl - t0) < R ? (nl - t0) : R);
-    const int r = lane / S, sl = lane - (lane / S) * S;
-    const bool in_tile = r < R;
-    const bool active = r < rows_here;
-    const int64_t il = t0 + (active ? r : 0);
-    const int64_t row0 = line * nl + t0;
+    if (task >= n_tasks) return;                   // whole wave leaves; no block barriers below
+    const Tile t = make_tile<D>(sp, task, tiles_per_line, R, S, lane);
+    if (tile_banded<D, P>(sp, t))
+        forward_body<T, P, D, WHAT, FINAL, true, WPB, R>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
+    else
+        forward_body<T, P, D, WHAT, FINAL, false, WPB, R>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
+}
 
-    // grid offset of this row's point (q1, [q2,] 0)
-    const int64_t N2 = sp.N[1], N3 = (D == 3) ? sp.N[2] : 1;
-    int64_t base;
-    if constexpr (D == 3) base = ((i1 * Q) * N2 + i2 * Q) * N3 + il * Q;
-    else base = (i1 * Q) * N2 + il * Q;
+// --------------------------------------------------------------------------------------
+// Adjoint.  Lane (r, q_d): row r of the tile, node column q_d of the last direction.
+// The upstream gradient of the tile is staged one s1 slab at a time (the next slab's
+// global loads are in flight while the current one is contracted); each slab reduces
+// to Z[s1][q2] in registers, and the final pass over s1 gives every output directly.
+template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R>
+struct Adjoint {
+    static constexpr int Q = P + 1, S = 2 * P + 1;
+    static constexpr int SL = (D == 3) ? S * S : S;     // slots of one s1 slab
+    static constexpr int SD = S * SL;
+    static constexpr int S3P = (S + 3) & ~3;            // LDS row of one (s1, s2): padded to 16 B
+    static constexpr int SLP = ((D == 3) ? S * S3P : S3P) + 4;
+    static constexpr int NPF = (R * SL + 63) / 64;      // prefetch registers per lane
+    static constexpr int NQ2 = (D == 3) ? Q : 1;
+    using FT = typename FinalTab<T, FINAL>::type;
 
-    // table rows: leading directions uniform, last direction per lane
-    const T *tM[3], *tK[3];
-    const FT *fM1 = final_table<T, FINAL>(tb, 0, 0) + i1 * Q * S;
-    const FT *fK1 = final_table<T, FINAL>(tb, 1, 0) + i1 * Q * S;
+    const DevSpace &sp;
+    const Tile &t;
+    T *stage;          // R * SLP values of this wave
+    int lane, ql;
+
+    __device__ __forceinline__ void load_slab(const T *__restrict__ g, int s1, T (&pf)[NPF]) const {
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const int64_t ik = (k == 0) ? i1 : (k == D - 1 ? il : i2);
-        tM[k] = (const T *)tb.t[0][k] + ik * Q * S;
-        tK[k] = (const T *)tb.t[1][k] + ik * Q * S;
+        for (int k = 0; k < NPF; ++k) {
+            const int e = lane + 64 * k;
+            T v = T(0);
+            if (e < t.rows_here * SL) {
+                const int rr = e / SL, tt = e - (e / SL) * SL;
+                bool ok;
+                if constexpr (D == 3) {
+                    const int64_t j2 = t.i2 - P + tt / S, j3 = t.t0 + rr - P + tt % S;
+                    ok = j2 >= 0 && j2 < sp.n[1] && j3 >= 0 && j3 < t.nl;
+                } else {
+                    const int64_t j2 = t.t0 + rr - P + tt;
+                    ok = j2 >= 0 && j2 < t.nl;
+                }
+                if (ok) v = g[(t.row0 * SD + (int64_t)s1 * SL) + (uint32_t)(rr * SD + tt)];
+            }
+            pf[k] = v;
+        }
     }
-    const bool col_ok_last = (il - P + sl >= 0) && (il - P + sl < nl);
 
-    if constexpr (D == 3) {
-        // V[s2][q1] for each needed set; M: c; K: term 1 (a0) and terms 2+3 (a1 + a2)
-        T Vm[S][Q], V1[S][Q], V23[S][Q];
-        auto contract = [&](const T *__restrict__ f, const T *t3, const T *t2, T (&V)[S][Q], bool accumulate) {
-            T tl[Q];
+    __device__ __forceinline__ void store_slab(const T (&pf)[NPF]) const {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) tl[q] = t3[q * S + sl];
-            T U[Q][Q];
+        for (int k = 0; k < NPF; ++k) {
+            const int e = lane + 64 * k;
+            if (e < R * SL) {
+                const int rr = e / SL, tt = e - (e / SL) * SL;
+                const int s2 = (D == 3) ? tt / S : 0, s3 = (D == 3) ? tt % S : tt;
+                stage[rr * SLP + s2 * S3P + s3] = pf[k];
+            }
+        }
+    }
+
+    // Z[zi][q2] (+)= sum_{s2} (sum_{s3} G[s1][s2][s3] tl[s3]) t2[q2][s2] for NSET sets that
+    // share the slab (tl[m], t2[m]); d = 2: Z[zi][0] = sum_{s2} G[s1][s2] tl[s2].
+    template <int NSET, int NZ>
+    __device__ __forceinline__ void slab_contract(int zi, const T (&tl)[NSET][S], const cptr<T> (&t2)[NSET],
+                                                  T (&Z)[NSET][NZ][NQ2]) const {
+        const T *row = stage + (t.r < t.rows_here ? t.r : 0) * SLP;
+        if constexpr (D == 3) {
+#pragma unroll
+            for (int s2 = 0; s2 < S; ++s2) {
+                T g[S];
+#pragma unroll
+                for (int s3 = 0; s3 < S; ++s3) g[s3] = row[s2 * S3P + s3];
+#pragma unroll
+                for (int m = 0; m < NSET; ++m) {
+                    T y = T(0);
+#pragma unroll
+                    for (int s3 = 0; s3 < S; ++s3) y = fma(g[s3], tl[m][s3], y);
+#pragma unroll
+                    for (int q2 = 0; q2 < Q; ++q2)
+                        if (!BAND || in_band<P>(q2, s2)) Z[m][zi][q2] = fma(y, t2[m][q2 * S + s2], Z[m][zi][q2]);
+                }
+            }
+        } else {
+            T g[S];
+#pragma unroll
+            for (int s2 = 0; s2 < S; ++s2) g[s2] = row[s2];
+#pragma unroll
+            for (int m = 0; m < NSET; ++m) {
+                T y = T(0);
+#pragma unroll
+                for (int s2 = 0; s2 < S; ++s2) y = fma(g[s2], tl[m][s2], y);
+                Z[m][zi][0] = y;
+            }
+        }
+    }
+
+    // One pass over the s1 slabs of g, then the final pass over s1 and the stores.
+    // Plain accumulation (FINAL 0, and every FP64 call) keeps running sums over s1,
+    // Q x Q per set; the FP32 compensated and FP64-accumulated passes keep the S x Q
+    // slab results Z[s1][q2] and sum them at the end.
+    template <int NSET>
+    __device__ __forceinline__ void run(const T *__restrict__ g, const T (&tl)[NSET][S], const cptr<T> (&t2)[NSET],
+                                        const cptr<FT> (&f1)[NSET], T *const (&out)[NSET]) const {
+        constexpr bool RUNNING = (FINAL == 0);
+        constexpr int NZ = RUNNING ? 1 : S;
+        T Z[NSET][NZ][NQ2];
+        T acc[NSET][RUNNING ? Q : 1][NQ2];
+#pragma unroll
+        for (int m = 0; m < NSET; ++m) {
+#pragma unroll
+            for (int z = 0; z < NZ; ++z)
+#pragma unroll
+                for (int q2 = 0; q2 < NQ2; ++q2) Z[m][z][q2] = T(0);
+#pragma unroll
+            for (int z = 0; z < (RUNNING ? Q : 1); ++z)
+#pragma unroll
+                for (int q2 = 0; q2 < NQ2; ++q2) acc[m][z][q2] = T(0);
+        }
+        const int s1_lo = (int)(t.i1 >= P ? 0 : P - t.i1);
+        const int s1_hi = (int)(sp.n[0] - 1 - t.i1 + P < S - 1 ? sp.n[0] - 1 - t.i1 + P : S - 1);
+        T pf[NPF];
+        load_slab(g, s1_lo, pf);
+#pragma unroll
+        for (int s1 = 0; s1 < S; ++s1) {
+            if (s1 < s1_lo || s1 > s1_hi) continue;     // slab outside the space: contributes 0
+            store_slab(pf);
+            wave_lds_sync();
+            if (s1 + 1 <= s1_hi) load_slab(g, s1 + 1, pf);
+            if (t.in_tile) {
+                if constexpr (RUNNING) {
+#pragma unroll
+                    for (int m = 0; m < NSET; ++m)
+#pragma unroll
+                        for (int q2 = 0; q2 < NQ2; ++q2) Z[m][0][q2] = T(0);
+                    slab_contract<NSET, NZ>(0, tl, t2, Z);
+#pragma unroll
+                    for (int m = 0; m < NSET; ++m)
+#pragma unroll
+                        for (int q1 = 0; q1 < Q; ++q1)
+                            if (!BAND || in_band<P>(q1, s1))
+#pragma unroll
+                                for (int q2 = 0; q2 < NQ2; ++q2)
+                                    acc[m][q1][q2] = fma((T)f1[m][q1 * S + s1], Z[m][0][q2], acc[m][q1][q2]);
+                } else {
+                    slab_contract<NSET, NZ>(s1, tl, t2, Z);
+                }
+            }
+            wave_lds_sync();
+        }
+        if (!t.active) return;
+        const int64_t N2 = sp.N[1], N3 = (D == 3) ? sp.N[2] : 1;
+        const uint32_t lo = (uint32_t)(t.il * Q + ql);
+#pragma unroll
+        for (int m = 0; m < NSET; ++m)
 #pragma unroll
             for (int q1 = 0; q1 < Q; ++q1)
 #pragma unroll
-                for (int q2 = 0; q2 < Q; ++q2) {
-                    const T *src = f + base + ((int64_t)q1 * N2 + q2) * N3;
-                    T acc = T(0);
+                for (int q2 = 0; q2 < NQ2; ++q2) {
+                    T v;
+                    if constexpr (RUNNING) {
+                        v = acc[m][q1][q2];
+                    } else {
+                        Acc<T, FINAL> a;
 #pragma unroll
-                    for (int q3 = 0; q3 < Q; ++q3) acc = fma(src[q3], tl[q3], acc);
-                    U[q1][q2] = acc;
-                }
-#pragma unroll
-            for (int s2 = 0; s2 < S; ++s2)
-#pragma unroll
-                for (int q1 = 0; q1 < Q; ++q1) {
-                    T acc = accumulate ? V[s2][q1] : T(0);
-#pragma unroll
-                    for (int q2 = 0; q2 < Q; ++q2) acc = fma(U[q1][q2], t2[q2 * S + s2], acc);
-                    V[s2][q1] = acc;
-                }
-        };
-        if constexpr (DO_M) contract(cf, tM[2], tM[1], Vm, false);
-        if constexpr (DO_K) {
-            contract(a0, tM[2], tM[1], V1, false);     // term 1: K table in direction 1 (final pass)
-            contract(a1, tM[2], tK[1], V23, false);    // term 2: K table in direction 2
-            contract(a2, tK[2], tM[1], V23, true);     // term 3: K table in direction 3
-        }
-#pragma unroll
-        for (int s1 = 0; s1 < S; ++s1) {
-            const bool ok1 = (i1 - P + s1 >= 0) && (i1 - P + s1 < sp.n[0]);
-            if (in_tile) {
-#pragma unroll
-                for (int s2 = 0; s2 < S; ++s2) {
-                    const bool ok = ok1 && col_ok_last && (i2 - P + s2 >= 0) && (i2 - P + s2 < sp.n[1]);
-                    int m = 0;
-                    if constexpr (DO_M) {
-                        Acc<T, FINAL> acc;
-#pragma unroll
-                        for (int q1 = 0; q1 < Q; ++q1) acc.add(fM1[q1 * S + s1], Vm[s2][q1]);
-                        stage[wave][m][r * SL + s2 * S + sl] = ok ? acc.get() : T(0);
-                        ++m;
+                        for (int s1 = 0; s1 < S; ++s1)
+                            if (!BAND || in_band<P>(q1, s1)) a.add(f1[m][q1 * S + s1], Z[m][s1][q2]);
+                        v = a.get();
                     }
-                    if constexpr (DO_K) {
-                        Acc<T, FINAL> acc;
-#pragma unroll
-                        for (int q1 = 0; q1 < Q; ++q1) {
-                            acc.add(fK1[q1 * S + s1], V1[s2][q1]);
-                            acc.add(fM1[q1 * S + s1], V23[s2][q1]);
-                        }
-                        stage[wave][m][r * SL + s2 * S + sl] = ok ? acc.get() : T(0);
-                    }
+                    int64_t off;     // wave-uniform part; the lane adds il * Q + ql
+                    if constexpr (D == 3) off = ((t.i1 * Q + q1) * N2 + t.i2 * Q + q2) * N3;
+                    else off = (t.i1 * Q + q1) * N2;
+                    (out[m] + off)[lo] = v;
                 }
+    }
+};
+
+template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R>
+__device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &tb, const Tile &t, T *stage,
+                                             int lane, const T *__restrict__ gM, const T *__restrict__ gK,
+                                             T *__restrict__ dc, T *__restrict__ da0, T *__restrict__ da1,
+                                             T *__restrict__ da2) {
+    using A = Adjoint<T, P, D, FINAL, BAND, WPB, R>;
+    constexpr int Q = A::Q, S = A::S;
+    using FT = typename A::FT;
+    const int ql = lane - t.r * Q;
+    A adj{sp, t, stage, lane, ql};
+    const int64_t rs = (int64_t)Q * S;
+    cptr<T> M2 = table<T>(tb, 0, 1) + t.i2 * rs;
+    cptr<T> K2 = table<T>(tb, 1, 1) + t.i2 * rs;
+    const T *ML = (const T *)tb.t[0][D - 1] + t.il * rs + ql * S;
+    const T *KL = (const T *)tb.t[1][D - 1] + t.il * rs + ql * S;
+    cptr<FT> fM1 = final_table<T, FINAL>(tb, 0, 0) + t.i1 * rs;
+    cptr<FT> fK1 = final_table<T, FINAL>(tb, 1, 0) + t.i1 * rs;
+    T tlM[S], tlK[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        tlM[s] = ML[s];
+        tlK[s] = KL[s];
+    }
+    if constexpr ((WHAT & kWhatM) != 0) {
+        T tl[1][S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) tl[0][s] = tlM[s];
+        const cptr<T> t2[1] = {M2};
+        const cptr<FT> f1[1] = {fM1};
+        T *const out[1] = {dc};
+        adj.template run<1>(gM, tl, t2, f1, out);
+        phase_barrier();
+    }
+    if constexpr ((WHAT & kWhatK) != 0) {
+        if constexpr (D == 3) {
+            // term 1: (K, M, M), term 2: (M, K, M), term 3: (M, M, K) in directions (1, 2, 3)
+            T tl[3][S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                tl[0][s] = tlM[s];
+                tl[1][s] = tlM[s];
+                tl[2][s] = tlK[s];
             }
-            wave_lds_sync();
-            for (int e = lane; e < rows_here * SL; e += 64) {
-                const int rr = e / SL, t = e - (e / SL) * SL;
-                const int64_t off = (row0 + rr) * SD + s1 * SL + t;
-                int m = 0;
-                if constexpr (DO_M) { Mo[off] = stage[wave][m][e]; ++m; }
-                if constexpr (DO_K) Ko[off] = stage[wave][m][e];
+            const cptr<T> t2[3] = {M2, K2, M2};
+            const cptr<FT> f1[3] = {fK1, fM1, fM1};
+            T *const out[3] = {da0, da1, da2};
+            adj.template run<3>(gK, tl, t2, f1, out);
+        } else {
+            // term 1: (K, M), term 2: (M, K) in directions (1, 2)
+            T tl[2][S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                tl[0][s] = tlM[s];
+                tl[1][s] = tlK[s];
             }
-            wave_lds_sync();
-        }
-    } else {
-        T Um[Q], U1[Q], U2[Q];
-        auto contract = [&](const T *__restrict__ f, const T *t2, T (&U)[Q]) {
-            T tl[Q];
-#pragma unroll
-            for (int q = 0; q < Q; ++q) tl[q] = t2[q * S + sl];
-#pragma unroll
-            for (int q1 = 0; q1 < Q; ++q1) {
-                const T *src = f + base + (int64_t)q1 * N2;
-                T acc = T(0);
-#pragma unroll
-                for (int q2 = 0; q2 < Q; ++q2) acc = fma(src[q2], tl[q2], acc);
-                U[q1] = acc;
-            }
-        };
-        if constexpr (DO_M) contract(cf, tM[1], Um);
-        if constexpr (DO_K) {
-            contract(a0, tM[1], U1);   // term 1: K table in direction 1 (final pass)
-            contract(a1, tK[1], U2);   // term 2: K table in direction 2
-        }
-#pragma unroll
-        for (int s1 = 0; s1 < S; ++s1) {
-            const bool ok = col_ok_last && (i1 - P + s1 >= 0) && (i1 - P + s1 < sp.n[0]);
-            if (in_tile) {
-                int m = 0;
-                if constexpr (DO_M) {
-                    Acc<T, FINAL> acc;
-#pragma unroll
-                    for (int q1 = 0; q1 < Q; ++q1) acc.add(fM1[q1 * S + s1], Um[q1]);
-                    stage[wave][m][r * SL + sl] = ok ? acc.get() : T(0);
-                    ++m;
-                }
-                if constexpr (DO_K) {
-                    Acc<T, FINAL> acc;
-#pragma unroll
-                    for (int q1 = 0; q1 < Q; ++q1) {
-                        acc.add(fK1[q1 * S + s1], U1[q1]);
-                        acc.add(fM1[q1 * S + s1], U2[q1]);
-                    }
-                    stage[wave][m][r * SL + sl] = ok ? acc.get() : T(0);
-                }
-            }
-            wave_lds_sync();
-            for (int e = lane; e < rows_here * SL; e += 64) {
-                const int rr = e / SL, t = e - (e / SL) * SL;
-                const int64_t off = (row0 + rr) * SD + s1 * SL + t;
-                int m = 0;
-                if constexpr (DO_M) { Mo[off] = stage[wave][m][e]; ++m; }
-                if constexpr (DO_K) Ko[off] = stage[wave][m][e];
-            }
-            wave_lds_sync();
+            const cptr<T> t2[2] = {M2, M2};
+            const cptr<FT> f1[2] = {fK1, fM1};
+            T *const out[2] = {da0, da1};
+            adj.template run<2>(gK, tl, t2, f1, out);
         }
     }
 }
 
-// --------------------------------------------------------------------------------------
 template <typename T, int P, int D, int WHAT, int FINAL, int WPB>
 __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
     DevSpace sp, DevTabs tb, const T *__restrict__ gM, const T *__restrict__ gK,
     T *__restrict__ dc, T *__restrict__ da0, T *__restrict__ da1, T *__restrict__ da2,
     int64_t n_tasks, int tiles_per_line) {
-    constexpr int Q = P + 1, S = 2 * P + 1;
-    constexpr int R = 64 / Q;                     // rows per wave tile
-    constexpr int SL = (D == 3) ? S * S : S;
-    constexpr int SD = S * SL;
-    constexpr bool DO_M = (WHAT & kWhatM) != 0, DO_K = (WHAT & kWhatK) != 0;
-    constexpr int NG = (DO_M ? 1 : 0) + (DO_K ? 1 : 0);
-    constexpr int NQ = (D == 3) ? Q * Q : Q;      // outputs per lane per field
-    using FT = typename FinalTab<T, FINAL>::type;
-    __shared__ T stage[WPB][NG][R * SL];
-
-    const int wave = (int)(threadIdx.x >> 6);
+    constexpr int Q = P + 1;
+    constexpr int R = 64 / Q;                      // rows per wave tile
+    using A = Adjoint<T, P, D, FINAL, false, WPB, R>;
+    __shared__ __align__(16) T stage[WPB][R * A::SLP];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
     const int64_t task = (int64_t)blockIdx.x * WPB + wave;
     if (task >= n_tasks) return;
-    const int64_t line = task / tiles_per_line;
-    const int tile = (int)(task - line * tiles_per_line);
-    const int64_t nl = sp.n[D - 1];
-    int64_t i1, i2 = 0;
-    if constexpr (D == 3) {
-        i1 = line / sp.n[1];
-        i2 = line - i1 * sp.n[1];
-    } else {
-        i1 = line;
-    }
-    const int64_t t0 = (int64_t)tile * R;
-    const int rows_here = (int)((nl - t0) < R ? (nl - t0) : R);
-    const int r = lane / Q, ql = lane - (lane / Q) * Q;
-    const bool in_tile = r < R;
-    const bool active = r < rows_here;
-    const int64_t il = t0 + (active ? r : 0);
-    const int64_t row0 = line * nl + t0;
-
-    const T *tM[3], *tK[3];
-    const FT *fM1 = final_table<T, FINAL>(tb, 0, 0) + i1 * Q * S;
-    const FT *fK1 = final_table<T, FINAL>(tb, 1, 0) + i1 * Q * S;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const int64_t ik = (k == 0) ? i1 : (k == D - 1 ? il : i2);
-        tM[k] = (const T *)tb.t[0][k] + ik * Q * S;
-        tK[k] = (const T *)tb.t[1][k] + ik * Q * S;
-    }
-    // this lane's node column of the last-direction tables
-    T tlM[S], tlK[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        tlM[s] = tM[D - 1][ql * S + s];
-        tlK[s] = DO_K ? tK[D - 1][ql * S + s] : T(0);
-    }
-
-    // accumulators over s_1: index q1 * (D == 3 ? Q : 1) + q2
-    Acc<T, FINAL> accM[DO_M ? NQ : 1];
-    Acc<T, FINAL> accK[DO_K ? D : 1][DO_K ? NQ : 1];
-
-    for (int s1 = 0; s1 < S; ++s1) {
-        if (i1 - P + s1 < 0 || i1 - P + s1 >= sp.n[0]) continue;   // whole slab outside: zero
-        // stage the s1 slab of every row of the tile, slots outside the space zeroed
-        for (int e = lane; e < rows_here * SL; e += 64) {
-            const int rr = e / SL, t = e - (e / SL) * SL;
-            bool ok;
-            if constexpr (D == 3) {
-                const int64_t j2 = i2 - P + t / S, j3 = t0 + rr - P + t % S;
-                ok = j2 >= 0 && j2 < sp.n[1] && j3 >= 0 && j3 < nl;
-            } else {
-                const int64_t j2 = t0 + rr - P + t;
-                ok = j2 >= 0 && j2 < nl;
-            }
-            const int64_t off = (row0 + rr) * SD + (int64_t)s1 * SL + t;
-            int g = 0;
-            if constexpr (DO_M) { stage[wave][g][e] = ok ? gM[off] : T(0); ++g; }
-            if constexpr (DO_K) stage[wave][g][e] = ok ? gK[off] : T(0);
-        }
-        wave_lds_sync();
-        if (in_tile) {
-            const int rb = (r < rows_here ? r : 0) * SL;
-            if constexpr (D == 3) {
-                T Zm[Q], Z1[Q], Z2[Q], Z3[Q];
-#pragma unroll
-                for (int q = 0; q < Q; ++q) Zm[q] = Z1[q] = Z2[q] = Z3[q] = T(0);
-#pragma unroll
-                for (int s2 = 0; s2 < S; ++s2) {
-                    if constexpr (DO_M) {
-                        const T *g = &stage[wave][0][rb + s2 * S];
-                        T y = T(0);
-#pragma unroll
-                        for (int s3 = 0; s3 < S; ++s3) y = fma(g[s3], tlM[s3], y);
-#pragma unroll
-                        for (int q2 = 0; q2 < Q; ++q2) Zm[q2] = fma(y, tM[1][q2 * S + s2], Zm[q2]);
-                    }
-                    if constexpr (DO_K) {
-                        const T *g = &stage[wave][DO_M ? 1 : 0][rb + s2 * S];
-                        T y12 = T(0), y3 = T(0);
-#pragma unroll
-                        for (int s3 = 0; s3 < S; ++s3) {
-                            y12 = fma(g[s3], tlM[s3], y12);
-                            y3 = fma(g[s3], tlK[s3], y3);
-                        }
-#pragma unroll
-                        for (int q2 = 0; q2 < Q; ++q2) {
-                            Z1[q2] = fma(y12, tM[1][q2 * S + s2], Z1[q2]);
-                            Z2[q2] = fma(y12, tK[1][q2 * S + s2], Z2[q2]);
-                            Z3[q2] = fma(y3, tM[1][q2 * S + s2], Z3[q2]);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int q1 = 0; q1 < Q; ++q1)
-#pragma unroll
-                    for (int q2 = 0; q2 < Q; ++q2) {
-                        if constexpr (DO_M) accM[q1 * Q + q2].add(fM1[q1 * S + s1], Zm[q2]);
-                        if constexpr (DO_K) {
-                            accK[0][q1 * Q + q2].add(fK1[q1 * S + s1], Z1[q2]);
-                            accK[1][q1 * Q + q2].add(fM1[q1 * S + s1], Z2[q2]);
-                            accK[2][q1 * Q + q2].add(fM1[q1 * S + s1], Z3[q2]);
-                        }
-                    }
-            } else {
-                if constexpr (DO_M) {
-                    const T *g = &stage[wave][0][rb];
-                    T y = T(0);
-#pragma unroll
-                    for (int s2 = 0; s2 < S; ++s2) y = fma(g[s2], tlM[s2], y);
-#pragma unroll
-                    for (int q1 = 0; q1 < Q; ++q1) accM[q1].add(fM1[q1 * S + s1], y);
-                }
-                if constexpr (DO_K) {
-                    const T *g = &stage[wave][DO_M ? 1 : 0][rb];
-                    T y1 = T(0), y2 = T(0);
-#pragma unroll
-                    for (int s2 = 0; s2 < S; ++s2) {
-                        y1 = fma(g[s2], tlM[s2], y1);
-                        y2 = fma(g[s2], tlK[s2], y2);
-                    }
-#pragma unroll
-                    for (int q1 = 0; q1 < Q; ++q1) {
-                        accK[0][q1].add(fK1[q1 * S + s1], y1);
-                        accK[1][q1].add(fM1[q1 * S + s1], y2);
-                    }
-                }
-            }
-        }
-        wave_lds_sync();
-    }
-
-    if (!active) return;
-    const int64_t N2 = sp.N[1], N3 = (D == 3) ? sp.N[2] : 1;
-#pragma unroll
-    for (int q1 = 0; q1 < Q; ++q1) {
-        if constexpr (D == 3) {
-#pragma unroll
-            for (int q2 = 0; q2 < Q; ++q2) {
-                const int64_t off = ((i1 * Q + q1) * N2 + i2 * Q + q2) * N3 + il * Q + ql;
-                if constexpr (DO_M) dc[off] = accM[q1 * Q + q2].get();
-                if constexpr (DO_K) {
-                    da0[off] = accK[0][q1 * Q + q2].get();
-                    da1[off] = accK[1][q1 * Q + q2].get();
-                    da2[off] = accK[2][q1 * Q + q2].get();
-                }
-            }
-        } else {
-            const int64_t off = (i1 * Q + q1) * N2 + il * Q + ql;
-            if constexpr (DO_M) dc[off] = accM[q1].get();
-            if constexpr (DO_K) {
-                da0[off] = accK[0][q1].get();
-                da1[off] = accK[1][q1].get();
-            }
-        }
-    }
+    const Tile t = make_tile<D>(sp, task, tiles_per_line, R, Q, lane);
+    if (tile_banded<D, P>(sp, t))
+        adjoint_body<T, P, D, WHAT, FINAL, true, WPB, R>(sp, tb, t, stage[wave], lane, gM, gK, dc, da0, da1, da2);
+    else
+        adjoint_body<T, P, D, WHAT, FINAL, false, WPB, R>(sp, tb, t, stage[wave], lane, gM, gK, dc, da0, da1, da2);
 }
 
 // --- dispatch ----------------------------------------------------------------------------
