@@ -28,6 +28,9 @@
  *               uses the stiffness-rule nodes in direction k and mass-rule nodes in
  *               the other directions.  wqa_get_rules returns those coordinates.
  *
+ * Alignment: every device buffer (coefficients, matrices, gradients) must start on a
+ * 16-byte boundary (hipMalloc and PyTorch allocations do); WQA_EINVAL otherwise.
+ *
  * Ownership: every device buffer passed in belongs to the caller; the library owns
  * the context and its (small) rule tables on host and device.  The assemble calls
  * never allocate, run asynchronously on the given HIP stream (NULL = default
@@ -95,7 +98,8 @@ wqa_status wqa_set_space(wqa_ctx *ctx, int dim, int degree, const int64_t *n_ele
 
 /* Installs the default rules for both kinds in every direction: the paper's
  * interior rules (eq:WQquadratic, eq:WQcubic, eq:WQquadraticStiff, eq:WQcubicStiff),
- * solved on the host by Newton in FP64 from the exactness conditions, translated to
+ * solved on the host by Newton (x87 extended precision, rounded once to FP64) from
+ * the exactness conditions, translated to
  * every interior row; and, for the p rows at each end that the paper leaves open
  * (Remark closing Sec. 3.2), weighted Gaussian rules of at most p+1 nodes solved the
  * same way (exactness on the row's interacting functions, completed by degree-

@@ -704,10 +704,17 @@ void fill(const wqa_ctx *c, wqa::DevSpace &sp, wqa::DevTabs &tb, wqa_dtype dtype
     }
 }
 
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
 wqa_status forward(wqa_ctx *c, const char *who, wqa_dtype dtype, int what, const void *cf,
                    const void *const *a, void *M, void *K, void *stream) {
     wqa_status st = ready(c, who, dtype);
     if (st != WQA_OK) return st;
+    if (!aligned16(cf) || !aligned16(M) || !aligned16(K))
+        return fail(WQA_EINVAL, "%s: device buffers must be 16-byte aligned", who);
+    if (a)
+        for (int k = 0; k < c->dim; ++k)
+            if (!aligned16(a[k])) return fail(WQA_EINVAL, "%s: a[%d] is not 16-byte aligned", who, k);
     if ((what & wqa::kWhatM) && (!cf || !M)) return fail(WQA_EINVAL, "%s: c and M must be non-NULL", who);
     if (what & wqa::kWhatK) {
         if (!a || !K) return fail(WQA_EINVAL, "%s: a and K must be non-NULL", who);
@@ -750,8 +757,12 @@ wqa_status wqa_assemble_adjoint(wqa_ctx *c, wqa_dtype dtype, const void *gM, con
     if ((gM == nullptr) != (dc == nullptr)) return fail(WQA_EINVAL, "%s: dc must be given exactly when gM is", who);
     if ((gK == nullptr) != (da == nullptr)) return fail(WQA_EINVAL, "%s: da must be given exactly when gK is", who);
     if (da)
-        for (int k = 0; k < c->dim; ++k)
+        for (int k = 0; k < c->dim; ++k) {
             if (!da[k]) return fail(WQA_EINVAL, "%s: da[%d] is NULL", who, k);
+            if (!aligned16(da[k])) return fail(WQA_EINVAL, "%s: da[%d] is not 16-byte aligned", who, k);
+        }
+    if (!aligned16(gM) || !aligned16(gK) || !aligned16(dc))
+        return fail(WQA_EINVAL, "%s: device buffers must be 16-byte aligned", who);
     int what = (gM ? wqa::kWhatM : 0) | (gK ? wqa::kWhatK : 0);
     wqa::DevSpace sp;
     wqa::DevTabs tb;

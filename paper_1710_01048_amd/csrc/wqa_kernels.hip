@@ -108,6 +108,21 @@ __device__ __forceinline__ void pin(T (&V)[A][B][C]) {
     for (int a = 0; a < A; ++a) pin(V[a]);
 }
 
+template <typename T, int A>
+__device__ __forceinline__ void pin(T (&V)[A]) {
+#pragma unroll
+    for (int a = 0; a < A; ++a) asm volatile("" : "+v"(V[a]));
+}
+
+// Makes a wave-uniform table pointer opaque at this point: table reads through it are
+// then issued after here instead of all being hoisted to the top of the kernel, which
+// would keep every table value of every phase in scalar registers at once.
+template <typename T>
+__device__ __forceinline__ cptr<T> fresh(cptr<T> p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
 // Rows whose nodes sit one per element of their support (every row but the p at each
 // end of a direction) have tables that vanish outside q <= s <= q + P: node q only
 // meets the P+1 functions living on its element.  The banded code paths skip those
@@ -174,7 +189,7 @@ __device__ __forceinline__ bool tile_banded(const DevSpace &sp, const Tile &t) {
 
 // --------------------------------------------------------------------------------------
 // Forward.  Lane (r, s_d): row r of the tile, slot column s_d of the last direction.
-template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R>
+template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R, bool FULL>
 struct Forward {
     static constexpr int Q = P + 1, S = 2 * P + 1;
     static constexpr int SL = (D == 3) ? S * S : S;
@@ -184,7 +199,7 @@ struct Forward {
     const DevSpace &sp;
     const DevTabs &tb;
     const Tile &t;
-    T *stage;          // R * SL values of this wave
+    T *stage;          // this wave's staging buffer (FULL: R * S^d + 16 B, else R * S^(d-1))
     int lane, sl;
     int64_t base;      // grid offset of this row's point (0, .., 0)
     int64_t N2, N3;
@@ -198,6 +213,7 @@ struct Forward {
         for (int q = 0; q < Q; ++q) tl[q] = t_last[q * S + sl];
         // wave-uniform part of the address, plus a 32-bit per-lane offset
         const uint32_t lo = (uint32_t)(t.il * Q);
+        t2 = fresh(t2);
         if constexpr (D == 3) {
             const T *fb = f + ((t.i1 * Q) * N2 + t.i2 * Q) * N3;
 #pragma unroll
@@ -236,15 +252,25 @@ struct Forward {
     }
 
     // Final pass over q1 and store: X[s1][s2][sl] = sum_q1 fa[q1][s1] Va[s2][q1]
-    // (+ fb[q1][s1] Vb[s2][q1]), one s1 slab at a time through LDS.
+    // (+ fb[q1][s1] Vb[s2][q1]).
+    //  FULL:  the whole tile (rows_here x S^d values, one contiguous range of the output)
+    //         goes to LDS, shifted so that LDS and global addresses share their
+    //         alignment, then leaves with 16-byte vector stores.
+    //  !FULL: one s1 slab at a time (rows_here runs of S^(d-1) values), scalar stores.
     template <bool TWO>
     __device__ __forceinline__ void emit(cptr<FT> fa, const T (&Va)[S][Q], cptr<FT> fb, const T (&Vb)[S][Q],
                                          T *__restrict__ out) const {
         const bool ok_last = (t.il - P + sl >= 0) && (t.il - P + sl < t.nl);
         constexpr int NS2 = (D == 3) ? S : 1;
+        constexpr int VEC = 16 / (int)sizeof(T);
+        const int shift = FULL ? (int)((t.row0 * SD) & (VEC - 1)) : 0;
 #pragma unroll
         for (int s1 = 0; s1 < S; ++s1) {
             const bool ok1 = (t.i1 - P + s1 >= 0) && (t.i1 - P + s1 < sp.n[0]);
+            if constexpr (FULL) {          // (the slab path's divergent copy loop forbids it)
+                fa = fresh(fa);
+                if constexpr (TWO) fb = fresh(fb);
+            }
             if (t.in_tile) {
 #pragma unroll
                 for (int s2 = 0; s2 < NS2; ++s2) {
@@ -258,28 +284,53 @@ struct Forward {
                             if constexpr (TWO) acc.add(fb[q1 * S + s1], Vb[s2][q1]);
                         }
                     }
-                    stage[t.r * SL + s2 * S + sl] = ok ? acc.get() : T(0);
+                    const T v = ok ? acc.get() : T(0);
+                    if constexpr (FULL) stage[shift + t.r * SD + s1 * SL + s2 * S + sl] = v;
+                    else stage[t.r * SL + s2 * S + sl] = v;
                 }
             }
-            wave_lds_sync();
-            const int n_here = t.rows_here * SL;
-            T *ob = out + t.row0 * SD + s1 * SL;
+            if constexpr (!FULL) {
+                wave_lds_sync();
+                const int n_here = t.rows_here * SL;
+                T *ob = out + t.row0 * SD + s1 * SL;
 #pragma unroll 2
-            for (int e = lane; e < n_here; e += 64) {
-                const int rr = e / SL, tt = e - (e / SL) * SL;
-                ob[(uint32_t)(rr * SD + tt)] = stage[e];
+                for (int e = lane; e < n_here; e += 64) {
+                    const int rr = e / SL, tt = e - (e / SL) * SL;
+                    ob[(uint32_t)(rr * SD + tt)] = stage[e];
+                }
+                wave_lds_sync();
             }
+        }
+        if constexpr (FULL) {
+            wave_lds_sync();
+            const int n = t.rows_here * SD;
+            T *ob = out + t.row0 * SD;
+            const int head = (VEC - shift) & (VEC - 1);
+            if (lane < head && lane < n) ob[lane] = stage[shift + lane];
+            const int nvec = (n - head) / VEC;
+            for (int k = lane; k < nvec; k += 64) {
+                const int e = head + k * VEC;
+                if constexpr (sizeof(T) == 4) {
+                    const float4 v = *reinterpret_cast<const float4 *>(&stage[shift + e]);
+                    *reinterpret_cast<float4 *>(ob + (uint32_t)e) = v;
+                } else {
+                    const double2 v = *reinterpret_cast<const double2 *>(&stage[shift + e]);
+                    *reinterpret_cast<double2 *>(ob + (uint32_t)e) = v;
+                }
+            }
+            const int tail0 = head + nvec * VEC;
+            if (lane < n - tail0) ob[tail0 + lane] = stage[shift + tail0 + lane];
             wave_lds_sync();
         }
     }
 };
 
-template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R>
+template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R, bool FULL>
 __device__ __forceinline__ void forward_body(const DevSpace &sp, const DevTabs &tb, const Tile &t, T *stage,
                                              int lane, const T *__restrict__ cf, const T *__restrict__ a0,
                                              const T *__restrict__ a1, const T *__restrict__ a2,
                                              T *__restrict__ Mo, T *__restrict__ Ko) {
-    using F = Forward<T, P, D, FINAL, BAND, WPB, R>;
+    using F = Forward<T, P, D, FINAL, BAND, WPB, R, FULL>;
     constexpr int Q = F::Q, S = F::S;
     using FT = typename F::FT;
     F fw{sp, tb, t, stage, lane, lane - t.r * S, 0, sp.N[1], (D == 3) ? sp.N[2] : 1};
@@ -326,7 +377,7 @@ __device__ __forceinline__ void forward_body(const DevSpace &sp, const DevTabs &
     }
 }
 
-template <typename T, int P, int D, int WHAT, int FINAL, int WPB>
+template <typename T, int P, int D, int WHAT, int FINAL, int WPB, bool FULL>
 __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     DevSpace sp, DevTabs tb, const T *__restrict__ cf, const T *__restrict__ a0,
     const T *__restrict__ a1, const T *__restrict__ a2, T *__restrict__ Mo,
@@ -334,16 +385,17 @@ __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     constexpr int S = 2 * P + 1;
     constexpr int R = 64 / S;                      // rows per wave tile
     constexpr int SL = (D == 3) ? S * S : S;
-    __shared__ T stage[WPB][R * SL];
+    constexpr int STAGE = FULL ? R * S * SL + 16 / (int)sizeof(T) : R * SL;
+    __shared__ __align__(16) T stage[WPB][STAGE];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
     const int64_t task = (int64_t)blockIdx.x * WPB + wave;
     if (task >= n_tasks) return;                   // whole wave leaves; no block barriers below
     const Tile t = make_tile<D>(sp, task, tiles_per_line, R, S, lane);
     if (tile_banded<D, P>(sp, t))
-        forward_body<T, P, D, WHAT, FINAL, true, WPB, R>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
+        forward_body<T, P, D, WHAT, FINAL, true, WPB, R, FULL>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
     else
-        forward_body<T, P, D, WHAT, FINAL, false, WPB, R>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
+        forward_body<T, P, D, WHAT, FINAL, false, WPB, R, FULL>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
 }
 
 // --------------------------------------------------------------------------------------
@@ -367,37 +419,56 @@ struct Adjoint {
     T *stage;          // R * SLP values of this wave
     int lane, ql;
 
-    __device__ __forceinline__ void load_slab(const T *__restrict__ g, int s1, T (&pf)[NPF]) const {
+    // Per-lane staging map of one slab, the same for every s1: element k of this lane is
+    // slot tt of tile row rr (e = lane + 64 k = rr * SL + tt); goff is its offset inside the
+    // slab's rows, loff its LDS position (padded rows), bit k of valid says whether it
+    // exists and lies inside the space (else it stages as 0).
+    struct Map {
+        uint32_t goff[NPF], loff[NPF];
+        uint32_t valid;
+    };
+
+    __device__ __forceinline__ Map make_map() const {
+        Map m;
+        m.valid = 0;
+        const int i2 = (int)t.i2, t0 = (int)t.t0, nl = (int)t.nl, n2 = (int)sp.n[1];
 #pragma unroll
         for (int k = 0; k < NPF; ++k) {
             const int e = lane + 64 * k;
-            T v = T(0);
-            if (e < t.rows_here * SL) {
-                const int rr = e / SL, tt = e - (e / SL) * SL;
-                bool ok;
-                if constexpr (D == 3) {
-                    const int64_t j2 = t.i2 - P + tt / S, j3 = t.t0 + rr - P + tt % S;
-                    ok = j2 >= 0 && j2 < sp.n[1] && j3 >= 0 && j3 < t.nl;
-                } else {
-                    const int64_t j2 = t.t0 + rr - P + tt;
-                    ok = j2 >= 0 && j2 < t.nl;
-                }
-                if (ok) v = g[(t.row0 * SD + (int64_t)s1 * SL) + (uint32_t)(rr * SD + tt)];
+            const int rr = e / SL, tt = e - rr * SL;
+            const int s2 = (D == 3) ? tt / S : 0, s3 = (D == 3) ? tt - (tt / S) * S : tt;
+            m.goff[k] = (uint32_t)(rr * SD + tt);
+            m.loff[k] = (uint32_t)(rr * SLP + s2 * S3P + s3);
+            bool ok = e < t.rows_here * SL;
+            if constexpr (D == 3) {
+                const int j2 = i2 - P + s2, j3 = t0 + rr - P + s3;
+                ok = ok && j2 >= 0 && j2 < n2 && j3 >= 0 && j3 < nl;
+            } else {
+                const int j2 = t0 + rr - P + s3;
+                ok = ok && j2 >= 0 && j2 < nl;
             }
-            pf[k] = v;
+            m.valid |= (ok ? 1u : 0u) << k;
+        }
+        pin(m.goff);
+        pin(m.loff);
+        asm volatile("" : "+v"(m.valid));
+        return m;
+    }
+
+    __device__ __forceinline__ void load_slab(const T *__restrict__ g, int s1, const Map &m, T (&pf)[NPF]) const {
+        const T *gb = g + (t.row0 * SD + (int64_t)s1 * SL);       // wave-uniform
+#pragma unroll
+        for (int k = 0; k < NPF; ++k) {
+            const bool ok = (m.valid >> k) & 1u;
+            const T v = gb[ok ? m.goff[k] : 0u];                  // element 0 is always in bounds
+            pf[k] = ok ? v : T(0);
         }
     }
 
-    __device__ __forceinline__ void store_slab(const T (&pf)[NPF]) const {
+    __device__ __forceinline__ void store_slab(const Map &m, const T (&pf)[NPF]) const {
 #pragma unroll
-        for (int k = 0; k < NPF; ++k) {
-            const int e = lane + 64 * k;
-            if (e < R * SL) {
-                const int rr = e / SL, tt = e - (e / SL) * SL;
-                const int s2 = (D == 3) ? tt / S : 0, s3 = (D == 3) ? tt % S : tt;
-                stage[rr * SLP + s2 * S3P + s3] = pf[k];
-            }
-        }
+        for (int k = 0; k < NPF; ++k)
+            if (64 * (k + 1) <= R * SL || lane + 64 * k < R * SL) stage[m.loff[k]] = pf[k];
     }
 
     // Z[zi][q2] (+)= sum_{s2} (sum_{s3} G[s1][s2][s3] tl[s3]) t2[q2][s2] for NSET sets that
@@ -460,21 +531,29 @@ struct Adjoint {
         }
         const int s1_lo = (int)(t.i1 >= P ? 0 : P - t.i1);
         const int s1_hi = (int)(sp.n[0] - 1 - t.i1 + P < S - 1 ? sp.n[0] - 1 - t.i1 + P : S - 1);
+        const Map map = make_map();
         T pf[NPF];
-        load_slab(g, s1_lo, pf);
+        load_slab(g, s1_lo, map, pf);
 #pragma unroll
         for (int s1 = 0; s1 < S; ++s1) {
             if (s1 < s1_lo || s1 > s1_hi) continue;     // slab outside the space: contributes 0
-            store_slab(pf);
+            store_slab(map, pf);
             wave_lds_sync();
-            if (s1 + 1 <= s1_hi) load_slab(g, s1 + 1, pf);
+            if (s1 + 1 <= s1_hi) load_slab(g, s1 + 1, map, pf);
+            cptr<T> t2s[NSET];
+            cptr<FT> f1s[NSET];
+#pragma unroll
+            for (int m = 0; m < NSET; ++m) {
+                t2s[m] = fresh(t2[m]);
+                f1s[m] = fresh(f1[m]);
+            }
             if (t.in_tile) {
                 if constexpr (RUNNING) {
 #pragma unroll
                     for (int m = 0; m < NSET; ++m)
 #pragma unroll
                         for (int q2 = 0; q2 < NQ2; ++q2) Z[m][0][q2] = T(0);
-                    slab_contract<NSET, NZ>(0, tl, t2, Z);
+                    slab_contract<NSET, NZ>(0, tl, t2s, Z);
 #pragma unroll
                     for (int m = 0; m < NSET; ++m)
 #pragma unroll
@@ -482,9 +561,9 @@ struct Adjoint {
                             if (!BAND || in_band<P>(q1, s1))
 #pragma unroll
                                 for (int q2 = 0; q2 < NQ2; ++q2)
-                                    acc[m][q1][q2] = fma((T)f1[m][q1 * S + s1], Z[m][0][q2], acc[m][q1][q2]);
+                                    acc[m][q1][q2] = fma((T)f1s[m][q1 * S + s1], Z[m][0][q2], acc[m][q1][q2]);
                 } else {
-                    slab_contract<NSET, NZ>(s1, tl, t2, Z);
+                    slab_contract<NSET, NZ>(s1, tl, t2s, Z);
                 }
             }
             wave_lds_sync();
@@ -493,7 +572,8 @@ struct Adjoint {
         const int64_t N2 = sp.N[1], N3 = (D == 3) ? sp.N[2] : 1;
         const uint32_t lo = (uint32_t)(t.il * Q + ql);
 #pragma unroll
-        for (int m = 0; m < NSET; ++m)
+        for (int m = 0; m < NSET; ++m) {
+            const cptr<FT> f1m = fresh(f1[m]);
 #pragma unroll
             for (int q1 = 0; q1 < Q; ++q1)
 #pragma unroll
@@ -505,7 +585,7 @@ struct Adjoint {
                         Acc<T, FINAL> a;
 #pragma unroll
                         for (int s1 = 0; s1 < S; ++s1)
-                            if (!BAND || in_band<P>(q1, s1)) a.add(f1[m][q1 * S + s1], Z[m][s1][q2]);
+                            if (!BAND || in_band<P>(q1, s1)) a.add(f1m[q1 * S + s1], Z[m][s1][q2]);
                         v = a.get();
                     }
                     int64_t off;     // wave-uniform part; the lane adds il * Q + ql
@@ -513,6 +593,7 @@ struct Adjoint {
                     else off = (t.i1 * Q + q1) * N2;
                     (out[m] + off)[lo] = v;
                 }
+        }
     }
 };
 
@@ -618,7 +699,9 @@ hipError_t run_forward(const DevSpace &sp, const DevTabs &tb, const void *c, con
         a1 = (const T *)a[1];
         a2 = D == 3 ? (const T *)a[2] : nullptr;
     }
-    hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock>), dim3((unsigned)blocks),
+    // FP32: whole-tile staging with vector stores; FP64: s1 slabs (keeps LDS per wave small)
+    constexpr bool FULL = sizeof(T) == 4;
+    hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock, FULL>), dim3((unsigned)blocks),
                        dim3(64 * kWavesPerBlock), 0, st, sp, tb, (const T *)c, a0, a1, a2, (T *)M,
                        (T *)K, tasks, tiles);
     return hipGetLastError();

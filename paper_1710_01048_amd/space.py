@@ -105,14 +105,17 @@ class Space:
             raise ValueError(f"{name}: shape {tuple(t.shape)}, grid is {self.grid_shape}")
         if not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
+        if t.data_ptr() % 16:
+            raise ValueError(f"{name} must start on a 16-byte boundary")
         return t
 
     def _matrix(self, t, name, dtype):
         if t is None:
             return torch.empty(self.n_rows, self.slots_per_row, dtype=dtype, device=self.device)
         if t.device != self.device or t.dtype != dtype or not t.is_contiguous() or \
-                t.numel() != self.n_rows * self.slots_per_row:
-            raise ValueError(f"{name}: need contiguous {dtype} [{self.n_rows}, {self.slots_per_row}] on {self.device}")
+                t.numel() != self.n_rows * self.slots_per_row or t.data_ptr() % 16:
+            raise ValueError(f"{name}: need contiguous, 16-byte aligned {dtype} [{self.n_rows}, "
+                             f"{self.slots_per_row}] on {self.device}")
         return t
 
     def _need_device(self):
