@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample size (0: calibrate to ~15 s)")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     return ap.parse_args()
 
 
@@ -159,6 +161,14 @@ def main():
     import paper_1710_01048_amd as wqa
     assert torch.cuda.is_available(), "needs a HIP device"
     dev = torch.device("cuda:0")
+    if args.profile_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: 3 x 1 GiB read + 1 GiB written")
     sp = wqa.Space(3, P, NEL, device=dev)
     sp.set_final_mode(FINAL_MODE)
     nnz_mat = sp.n_rows * sp.slots_per_row

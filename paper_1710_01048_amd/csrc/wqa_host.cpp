@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -691,7 +692,19 @@ wqa_status ready(wqa_ctx *c, const char *who, wqa_dtype dtype) {
     return WQA_OK;
 }
 
+// Tuning knobs read once from the environment: WQA_KERNEL_FLAGS (bit 0: XCD-aware
+// work-group order, bit 1: nontemporal output stores; default 1) and WQA_FWD_STAGE
+// (forward output staging 0 slab / 1 whole tile / 2 direct; default per dtype).
+int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
 void fill(const wqa_ctx *c, wqa::DevSpace &sp, wqa::DevTabs &tb, wqa_dtype dtype) {
+    static const int flags = env_int("WQA_KERNEL_FLAGS", wqa::kFlagXcdRemap);
+    static const int stage = env_int("WQA_FWD_STAGE", -1);
+    sp.flags = flags;
+    sp.stage = stage;
     sp.d = c->dim;
     sp.p = c->p;
     for (int k = 0; k < wqa::kMaxDim; ++k) {

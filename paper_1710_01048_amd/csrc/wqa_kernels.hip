@@ -149,6 +149,18 @@ __device__ __forceinline__ void load_q(const T *__restrict__ p, T (&v)[Q]) {
     }
 }
 
+enum { kStageSlab = 0, kStageFull = 1, kStageDirect = 2 };
+
+// Work-group index, optionally remapped so that consecutive indices run on the same
+// XCD: the hardware deals work-groups round-robin over the 8 XCDs (each with its own
+// L2), and neighbouring tiles share the cache lines at their boundaries.
+__device__ __forceinline__ uint32_t block_index(int flags) {
+    const uint32_t b = blockIdx.x;
+    if (!(flags & kFlagXcdRemap)) return b;
+    const uint32_t nb = gridDim.x, q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Per-wave tile context shared by the forward and adjoint bodies.
 struct Tile {
     int64_t i1, i2, t0, row0, il, nl;
@@ -189,8 +201,9 @@ __device__ __forceinline__ bool tile_banded(const DevSpace &sp, const Tile &t) {
 
 // --------------------------------------------------------------------------------------
 // Forward.  Lane (r, s_d): row r of the tile, slot column s_d of the last direction.
-template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R, bool FULL>
+template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R, int STG>
 struct Forward {
+    static constexpr bool FULL = STG == kStageFull, DIRECT = STG == kStageDirect;
     static constexpr int Q = P + 1, S = 2 * P + 1;
     static constexpr int SL = (D == 3) ? S * S : S;
     static constexpr int SD = S * SL;
@@ -199,10 +212,15 @@ struct Forward {
     const DevSpace &sp;
     const DevTabs &tb;
     const Tile &t;
-    T *stage;          // this wave's staging buffer (FULL: R * S^d + 16 B, else R * S^(d-1))
+    T *stage;          // this wave's staging buffer (FULL: R * S^d + 16 B, SLAB: R * S^(d-1))
     int lane, sl;
-    int64_t base;      // grid offset of this row's point (0, .., 0)
+    bool nt;           // nontemporal output stores
     int64_t N2, N3;
+
+    __device__ __forceinline__ void store(T *base_u, uint32_t off, T v) const {
+        if (nt) __builtin_nontemporal_store(v, base_u + off);
+        else base_u[off] = v;
+    }
 
     // V[s2][q1] = sum_{q2} sum_{q3} f[q1][q2][q3] t3[q3][sl] t2[q2][s2]     (d = 3)
     // V[0][q1]  = sum_{q2} f[q1][q2] t2[q2][sl]                            (d = 2)
@@ -256,7 +274,8 @@ struct Forward {
     //  FULL:  the whole tile (rows_here x S^d values, one contiguous range of the output)
     //         goes to LDS, shifted so that LDS and global addresses share their
     //         alignment, then leaves with 16-byte vector stores.
-    //  !FULL: one s1 slab at a time (rows_here runs of S^(d-1) values), scalar stores.
+    //  SLAB:  one s1 slab at a time (rows_here runs of S^(d-1) values), scalar stores.
+    //  DIRECT: no LDS; every lane stores its own values (runs of S per row).
     template <bool TWO>
     __device__ __forceinline__ void emit(cptr<FT> fa, const T (&Va)[S][Q], cptr<FT> fb, const T (&Vb)[S][Q],
                                          T *__restrict__ out) const {
@@ -285,18 +304,23 @@ struct Forward {
                         }
                     }
                     const T v = ok ? acc.get() : T(0);
-                    if constexpr (FULL) stage[shift + t.r * SD + s1 * SL + s2 * S + sl] = v;
-                    else stage[t.r * SL + s2 * S + sl] = v;
+                    if constexpr (FULL) {
+                        stage[shift + t.r * SD + s1 * SL + s2 * S + sl] = v;
+                    } else if constexpr (DIRECT) {
+                        if (t.active) store(out + t.row0 * SD + s1 * SL + s2 * S, (uint32_t)(t.r * SD + sl), v);
+                    } else {
+                        stage[t.r * SL + s2 * S + sl] = v;
+                    }
                 }
             }
-            if constexpr (!FULL) {
+            if constexpr (STG == kStageSlab) {
                 wave_lds_sync();
                 const int n_here = t.rows_here * SL;
                 T *ob = out + t.row0 * SD + s1 * SL;
 #pragma unroll 2
                 for (int e = lane; e < n_here; e += 64) {
                     const int rr = e / SL, tt = e - (e / SL) * SL;
-                    ob[(uint32_t)(rr * SD + tt)] = stage[e];
+                    store(ob, (uint32_t)(rr * SD + tt), stage[e]);
                 }
                 wave_lds_sync();
             }
@@ -306,36 +330,33 @@ struct Forward {
             const int n = t.rows_here * SD;
             T *ob = out + t.row0 * SD;
             const int head = (VEC - shift) & (VEC - 1);
-            if (lane < head && lane < n) ob[lane] = stage[shift + lane];
+            if (lane < head && lane < n) store(ob, (uint32_t)lane, stage[shift + lane]);
             const int nvec = (n - head) / VEC;
+            using V = T __attribute__((ext_vector_type(VEC)));
             for (int k = lane; k < nvec; k += 64) {
                 const int e = head + k * VEC;
-                if constexpr (sizeof(T) == 4) {
-                    const float4 v = *reinterpret_cast<const float4 *>(&stage[shift + e]);
-                    *reinterpret_cast<float4 *>(ob + (uint32_t)e) = v;
-                } else {
-                    const double2 v = *reinterpret_cast<const double2 *>(&stage[shift + e]);
-                    *reinterpret_cast<double2 *>(ob + (uint32_t)e) = v;
-                }
+                const V v = *reinterpret_cast<const V *>(&stage[shift + e]);
+                V *dst = reinterpret_cast<V *>(ob + (uint32_t)e);
+                if (nt) __builtin_nontemporal_store(v, dst);
+                else *dst = v;
             }
             const int tail0 = head + nvec * VEC;
-            if (lane < n - tail0) ob[tail0 + lane] = stage[shift + tail0 + lane];
+            if (lane < n - tail0) store(ob, (uint32_t)(tail0 + lane), stage[shift + tail0 + lane]);
             wave_lds_sync();
         }
     }
 };
 
-template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R, bool FULL>
+template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R, int STG>
 __device__ __forceinline__ void forward_body(const DevSpace &sp, const DevTabs &tb, const Tile &t, T *stage,
                                              int lane, const T *__restrict__ cf, const T *__restrict__ a0,
                                              const T *__restrict__ a1, const T *__restrict__ a2,
                                              T *__restrict__ Mo, T *__restrict__ Ko) {
-    using F = Forward<T, P, D, FINAL, BAND, WPB, R, FULL>;
+    using F = Forward<T, P, D, FINAL, BAND, WPB, R, STG>;
     constexpr int Q = F::Q, S = F::S;
     using FT = typename F::FT;
-    F fw{sp, tb, t, stage, lane, lane - t.r * S, 0, sp.N[1], (D == 3) ? sp.N[2] : 1};
-    if constexpr (D == 3) fw.base = ((t.i1 * Q) * fw.N2 + t.i2 * Q) * fw.N3 + t.il * Q;
-    else fw.base = (t.i1 * Q) * fw.N2 + t.il * Q;
+    F fw{sp, tb, t, stage, lane, lane - t.r * S, (sp.flags & kFlagNontemporal) != 0, sp.N[1],
+         (D == 3) ? sp.N[2] : 1};
     const int64_t rs = (int64_t)Q * S;
     cptr<T> M2 = table<T>(tb, 0, 1) + (D == 3 ? t.i2 : 0) * rs;
     cptr<T> K2 = table<T>(tb, 1, 1) + (D == 3 ? t.i2 : 0) * rs;
@@ -377,7 +398,7 @@ __device__ __forceinline__ void forward_body(const DevSpace &sp, const DevTabs &
     }
 }
 
-template <typename T, int P, int D, int WHAT, int FINAL, int WPB, bool FULL>
+template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int STG>
 __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     DevSpace sp, DevTabs tb, const T *__restrict__ cf, const T *__restrict__ a0,
     const T *__restrict__ a1, const T *__restrict__ a2, T *__restrict__ Mo,
@@ -385,17 +406,17 @@ __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     constexpr int S = 2 * P + 1;
     constexpr int R = 64 / S;                      // rows per wave tile
     constexpr int SL = (D == 3) ? S * S : S;
-    constexpr int STAGE = FULL ? R * S * SL + 16 / (int)sizeof(T) : R * SL;
+    constexpr int STAGE = STG == kStageFull ? R * S * SL + 16 / (int)sizeof(T) : (STG == kStageSlab ? R * SL : 1);
     __shared__ __align__(16) T stage[WPB][STAGE];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t task = (int64_t)blockIdx.x * WPB + wave;
+    const int64_t task = (int64_t)block_index(sp.flags) * WPB + wave;
     if (task >= n_tasks) return;                   // whole wave leaves; no block barriers below
     const Tile t = make_tile<D>(sp, task, tiles_per_line, R, S, lane);
     if (tile_banded<D, P>(sp, t))
-        forward_body<T, P, D, WHAT, FINAL, true, WPB, R, FULL>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
+        forward_body<T, P, D, WHAT, FINAL, true, WPB, R, STG>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
     else
-        forward_body<T, P, D, WHAT, FINAL, false, WPB, R, FULL>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
+        forward_body<T, P, D, WHAT, FINAL, false, WPB, R, STG>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
 }
 
 // --------------------------------------------------------------------------------------
@@ -671,7 +692,7 @@ __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
     __shared__ __align__(16) T stage[WPB][R * A::SLP];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t task = (int64_t)blockIdx.x * WPB + wave;
+    const int64_t task = (int64_t)block_index(sp.flags) * WPB + wave;
     if (task >= n_tasks) return;
     const Tile t = make_tile<D>(sp, task, tiles_per_line, R, Q, lane);
     if (tile_banded<D, P>(sp, t))
@@ -699,11 +720,18 @@ hipError_t run_forward(const DevSpace &sp, const DevTabs &tb, const void *c, con
         a1 = (const T *)a[1];
         a2 = D == 3 ? (const T *)a[2] : nullptr;
     }
-    // FP32: whole-tile staging with vector stores; FP64: s1 slabs (keeps LDS per wave small)
-    constexpr bool FULL = sizeof(T) == 4;
-    hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock, FULL>), dim3((unsigned)blocks),
-                       dim3(64 * kWavesPerBlock), 0, st, sp, tb, (const T *)c, a0, a1, a2, (T *)M,
-                       (T *)K, tasks, tiles);
+    // default: FP32 whole-tile staging with vector stores; FP64 s1 slabs (LDS per wave)
+    const int stg = sp.stage >= 0 ? sp.stage : (sizeof(T) == 4 ? (int)kStageFull : (int)kStageSlab);
+    const dim3 grid((unsigned)blocks), block(64 * kWavesPerBlock);
+    if (stg == kStageFull)
+        hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock, kStageFull>), grid, block, 0, st, sp,
+                           tb, (const T *)c, a0, a1, a2, (T *)M, (T *)K, tasks, tiles);
+    else if (stg == kStageDirect)
+        hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock, kStageDirect>), grid, block, 0, st,
+                           sp, tb, (const T *)c, a0, a1, a2, (T *)M, (T *)K, tasks, tiles);
+    else
+        hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock, kStageSlab>), grid, block, 0, st, sp,
+                           tb, (const T *)c, a0, a1, a2, (T *)M, (T *)K, tasks, tiles);
     return hipGetLastError();
 }
 
