@@ -63,6 +63,31 @@ def make_inputs(sp, dtype):
     return fields, gM, gK
 
 
+def hbm_probe(dev, gib=2, reps=5):
+    """Achievable HBM bandwidth on this machine from plain PyTorch kernels on `gib` GiB
+    buffers: write-only (fill), read-only (sum) and copy; GB/s of bytes moved."""
+    n = (gib << 30) // 4
+    a = torch.empty(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    out = {}
+    for name, fn, nbytes in (("write", lambda: a.fill_(2.0), 4 * n),
+                             ("read", lambda: a.sum(), 4 * n),
+                             ("copy", lambda: b.copy_(a), 8 * n)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_GBs"] = nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return out
+
+
 def run_steps(sp, fields, gM, gK, steps, warmup):
     """Times `steps` steps (forward + adjoint) with HIP events on the launch stream."""
     M = torch.empty(sp.n_rows, sp.slots_per_row, dtype=fields[0].dtype, device=sp.device)
@@ -222,6 +247,8 @@ def main():
         g64 = (gM64, gK64)
         del f64
 
+    probe = hbm_probe(dev)
+    log(f"hbm probe: {probe}")
     line = {
         "metric": METRIC,
         "value": nnz_step / (step_ms * 1e-3),
@@ -247,6 +274,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": f"{dominant} (fused M+K, FP32)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes": fwd_bytes},
+        "hbm_probe_torch": probe,
     }
     if r64 is not None:
         fwd64, adj64 = float(np.mean(r64["fwd_ms"])), float(np.mean(r64["adj_ms"]))

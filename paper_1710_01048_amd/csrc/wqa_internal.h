@@ -21,6 +21,7 @@ struct DevSpace {
     int64_t N[kMaxDim];   // grid points per direction (n * (p + 1))
     int flags;            // Flags
     int stage;            // forward output staging (-1: default for the dtype)
+    int rows;             // forward rows per wave tile (0: 64 / (2p + 1))
 };
 
 // Contraction tables T[kind][dir] laid out [n_dir][Q][S] on the device, in the call's

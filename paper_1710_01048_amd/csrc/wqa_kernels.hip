@@ -222,15 +222,59 @@ struct Forward {
         else base_u[off] = v;
     }
 
+    // Input staging (whole-tile mode): the samples of every field the tile needs go to
+    // LDS first, each (q1[, q2]) line of the tile as one contiguous run of R rows x Q
+    // values, loaded with a few wide, non-redundant loads that are all in flight at once
+    // (in registers, the Q samples of a row would be loaded by each of its S lanes).
+    static constexpr bool INLDS = FULL;
+    static constexpr int NG = (D == 3) ? Q * Q : Q;     // lines per field
+    static constexpr int FSZ = NG * R * Q;              // staged values per field
+
+    template <int NF>
+    __device__ __forceinline__ void stage_fields(const T *const (&f)[NF]) const {
+        constexpr int U = (Q * (int)sizeof(T)) % 16 == 0 ? 16 / (int)sizeof(T) : 1;   // values per load
+        constexpr int PER = R * Q / U;                  // loads per line
+        constexpr int TOT = NG * PER;                   // loads per field
+        constexpr int IT = (TOT + 63) / 64;
+        using VT = T __attribute__((ext_vector_type(U)));
+        int64_t off[IT];
+        int lds[IT];
+        bool ok[IT];
+        const int64_t base = (D == 3) ? ((t.i1 * Q) * N2 + t.i2 * Q) * N3 + t.t0 * Q : (t.i1 * Q) * N2 + t.t0 * Q;
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int k = lane + 64 * it;
+            const int g = k / PER, e = (k - g * PER) * U;   // line and first value in it
+            ok[it] = k < TOT && e / Q < t.rows_here;
+            int64_t loff;
+            if constexpr (D == 3) loff = (int64_t)(g / Q) * N2 * N3 + (int64_t)(g % Q) * N3;
+            else loff = (int64_t)g * N2;
+            off[it] = ok[it] ? base + loff + e : base;
+            lds[it] = g * R * Q + e;
+        }
+        VT v[NF][IT];
+#pragma unroll
+        for (int m = 0; m < NF; ++m)
+#pragma unroll
+            for (int it = 0; it < IT; ++it) v[m][it] = *reinterpret_cast<const VT *>(f[m] + off[it]);
+#pragma unroll
+        for (int m = 0; m < NF; ++m)
+#pragma unroll
+            for (int it = 0; it < IT; ++it)
+                if (lane + 64 * it < TOT) *reinterpret_cast<VT *>(stage + m * FSZ + lds[it]) = ok[it] ? v[m][it] : VT(0);
+    }
+
     // V[s2][q1] = sum_{q2} sum_{q3} f[q1][q2][q3] t3[q3][sl] t2[q2][s2]     (d = 3)
     // V[0][q1]  = sum_{q2} f[q1][q2] t2[q2][sl]                            (d = 2)
-    __device__ __forceinline__ void contract(const T *__restrict__ f, const T *t_last, cptr<T> t2,
+    // Samples come from global memory (f) or, with input staging, from field slot fi.
+    __device__ __forceinline__ void contract(const T *__restrict__ f, int fi, const T *t_last, cptr<T> t2,
                                              T (&V)[S][Q], bool accumulate) const {
         T tl[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) tl[q] = t_last[q * S + sl];
         // wave-uniform part of the address, plus a 32-bit per-lane offset
         const uint32_t lo = (uint32_t)(t.il * Q);
+        const T *fs = stage + fi * FSZ + (t.r < t.rows_here ? t.r : 0) * Q;
         t2 = fresh(t2);
         if constexpr (D == 3) {
             const T *fb = f + ((t.i1 * Q) * N2 + t.i2 * Q) * N3;
@@ -240,7 +284,12 @@ struct Forward {
 #pragma unroll
                 for (int q2 = 0; q2 < Q; ++q2) {
                     T v[Q];
-                    load_q<T, Q>(fb + ((int64_t)q1 * N2 + q2) * N3 + lo, v);
+                    if constexpr (INLDS) {
+#pragma unroll
+                        for (int q3 = 0; q3 < Q; ++q3) v[q3] = fs[(q1 * Q + q2) * R * Q + q3];
+                    } else {
+                        load_q<T, Q>(fb + ((int64_t)q1 * N2 + q2) * N3 + lo, v);
+                    }
                     T acc = T(0);
 #pragma unroll
                     for (int q3 = 0; q3 < Q; ++q3) acc = fma(v[q3], tl[q3], acc);
@@ -260,7 +309,12 @@ struct Forward {
 #pragma unroll
             for (int q1 = 0; q1 < Q; ++q1) {
                 T v[Q];
-                load_q<T, Q>(fb + (int64_t)q1 * N2 + lo, v);
+                if constexpr (INLDS) {
+#pragma unroll
+                    for (int q2 = 0; q2 < Q; ++q2) v[q2] = fs[q1 * R * Q + q2];
+                } else {
+                    load_q<T, Q>(fb + (int64_t)q1 * N2 + lo, v);
+                }
                 T acc = accumulate ? V[0][q1] : T(0);
 #pragma unroll
                 for (int q2 = 0; q2 < Q; ++q2) acc = fma(v[q2], tl[q2], acc);
@@ -364,49 +418,77 @@ __device__ __forceinline__ void forward_body(const DevSpace &sp, const DevTabs &
     const T *KL = (const T *)tb.t[1][D - 1] + t.il * rs;
     cptr<FT> fM1 = final_table<T, FINAL>(tb, 0, 0) + t.i1 * rs;
     cptr<FT> fK1 = final_table<T, FINAL>(tb, 1, 0) + t.i1 * rs;
-    // The barriers keep each field's loads next to their use, so that the samples of
-    // only one field are live at a time (register pressure sets occupancy): the empty
-    // asm with a memory clobber stops loads from being hoisted across it, the
-    // scheduling barrier stops the machine scheduler from interleaving the phases.
-    if constexpr ((WHAT & kWhatM) != 0) {
-        T V[S][Q];
-        fw.contract(cf, ML, M2, V, false);
+    // Without input staging, the barriers keep each field's loads next to their use, so
+    // that the samples of only one field are live at a time (register pressure sets
+    // occupancy): the empty asm with a memory clobber stops loads from being hoisted
+    // across it, the scheduling barrier stops the machine scheduler from interleaving.
+    // With input staging every field is contracted before the first output is written
+    // (the outputs reuse the staging buffer).
+    constexpr bool DO_M = (WHAT & kWhatM) != 0, DO_K = (WHAT & kWhatK) != 0;
+    constexpr int NF = (DO_M ? 1 : 0) + (DO_K ? D : 0);
+    const int fk = DO_M ? 1 : 0;                  // field slot of a_1
+    if constexpr (F::INLDS) {
+        const T *fl[NF];
+        if constexpr (DO_M) fl[0] = cf;
+        if constexpr (DO_K) {
+            fl[fk] = a0;
+            fl[fk + 1] = a1;
+            if constexpr (D == 3) fl[fk + 2] = a2;
+        }
+        fw.template stage_fields<NF>(fl);
+        wave_lds_sync();
+    }
+    T V[DO_M ? S : 1][Q], V1[DO_K ? S : 1][Q], V2[DO_K ? S : 1][Q];
+    if constexpr (DO_M) {
+        fw.contract(cf, 0, ML, M2, V, false);
         pin(V);
         phase_barrier();
-        fw.template emit<false>(fM1, V, fM1, V, Mo);
-        phase_barrier();
+        if constexpr (!F::INLDS) {
+            fw.template emit<false>(fM1, V, fM1, V, Mo);
+            phase_barrier();
+        }
     }
-    if constexpr ((WHAT & kWhatK) != 0) {
-        T V1[S][Q], V2[S][Q];
+    if constexpr (DO_K) {
         if constexpr (D == 3) {
-            fw.contract(a0, ML, M2, V1, false);   // term 1: stiffness table in direction 1
+            fw.contract(a0, fk, ML, M2, V1, false);       // term 1: stiffness table in direction 1
             pin(V1);
             phase_barrier();
-            fw.contract(a1, ML, K2, V2, false);   // term 2: stiffness table in direction 2
+            fw.contract(a1, fk + 1, ML, K2, V2, false);   // term 2: stiffness table in direction 2
             pin(V2);
             phase_barrier();
-            fw.contract(a2, KL, M2, V2, true);    // term 3: stiffness table in direction 3
+            fw.contract(a2, fk + 2, KL, M2, V2, true);    // term 3: stiffness table in direction 3
         } else {
-            fw.contract(a0, ML, M2, V1, false);       // term 1: stiffness table in direction 1
+            fw.contract(a0, fk, ML, M2, V1, false);       // term 1: stiffness table in direction 1
             pin(V1);
             phase_barrier();
-            fw.contract(a1, KL, M2, V2, false);       // term 2: stiffness table in direction 2
+            fw.contract(a1, fk + 1, KL, M2, V2, false);   // term 2: stiffness table in direction 2
         }
         pin(V2);
         phase_barrier();
+    }
+    if constexpr (F::INLDS) {
+        wave_lds_sync();                                  // every lane done reading the samples
+        if constexpr (DO_M) {
+            fw.template emit<false>(fM1, V, fM1, V, Mo);
+            phase_barrier();
+        }
+    }
+    if constexpr (DO_K) {
         fw.template emit<true>(fK1, V1, fM1, V2, Ko);
     }
 }
 
-template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int STG>
+template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int STG, int R>
 __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     DevSpace sp, DevTabs tb, const T *__restrict__ cf, const T *__restrict__ a0,
     const T *__restrict__ a1, const T *__restrict__ a2, T *__restrict__ Mo,
     T *__restrict__ Ko, int64_t n_tasks, int tiles_per_line) {
-    constexpr int S = 2 * P + 1;
-    constexpr int R = 64 / S;                      // rows per wave tile
+    constexpr int S = 2 * P + 1;                   // R: rows per wave tile (<= 64 / S)
     constexpr int SL = (D == 3) ? S * S : S;
-    constexpr int STAGE = STG == kStageFull ? R * S * SL + 16 / (int)sizeof(T) : (STG == kStageSlab ? R * SL : 1);
+    constexpr int Q = P + 1, NG = (D == 3) ? Q * Q : Q;
+    constexpr int NF = ((WHAT & kWhatM) ? 1 : 0) + ((WHAT & kWhatK) ? D : 0);
+    constexpr int OUT = R * S * SL + 16 / (int)sizeof(T), IN = NF * NG * R * Q;
+    constexpr int STAGE = STG == kStageFull ? (OUT > IN ? OUT : IN) : (STG == kStageSlab ? R * SL : 1);
     __shared__ __align__(16) T stage[WPB][STAGE];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
@@ -704,10 +786,9 @@ __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
 // --- dispatch ----------------------------------------------------------------------------
 constexpr int kWavesPerBlock = 4;
 
-template <typename T, int P, int D, int WHAT, int FINAL>
-hipError_t run_forward(const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a,
-                       void *M, void *K, hipStream_t st) {
-    constexpr int S = 2 * P + 1, R = 64 / S;
+template <typename T, int P, int D, int WHAT, int FINAL, int STG, int R>
+hipError_t launch_fwd(const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a, void *M, void *K,
+                      hipStream_t st) {
     const int64_t nl = sp.n[D - 1];
     const int tiles = (int)((nl + R - 1) / R);
     int64_t lines = 1;
@@ -720,19 +801,24 @@ hipError_t run_forward(const DevSpace &sp, const DevTabs &tb, const void *c, con
         a1 = (const T *)a[1];
         a2 = D == 3 ? (const T *)a[2] : nullptr;
     }
+    hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock, STG, R>), dim3((unsigned)blocks),
+                       dim3(64 * kWavesPerBlock), 0, st, sp, tb, (const T *)c, a0, a1, a2, (T *)M, (T *)K, tasks,
+                       tiles);
+    return hipGetLastError();
+}
+
+template <typename T, int P, int D, int WHAT, int FINAL>
+hipError_t run_forward(const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a,
+                       void *M, void *K, hipStream_t st) {
+    constexpr int S = 2 * P + 1, R = 64 / S;
     // default: FP32 whole-tile staging with vector stores; FP64 s1 slabs (LDS per wave)
     const int stg = sp.stage >= 0 ? sp.stage : (sizeof(T) == 4 ? (int)kStageFull : (int)kStageSlab);
-    const dim3 grid((unsigned)blocks), block(64 * kWavesPerBlock);
-    if (stg == kStageFull)
-        hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock, kStageFull>), grid, block, 0, st, sp,
-                           tb, (const T *)c, a0, a1, a2, (T *)M, (T *)K, tasks, tiles);
-    else if (stg == kStageDirect)
-        hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock, kStageDirect>), grid, block, 0, st,
-                           sp, tb, (const T *)c, a0, a1, a2, (T *)M, (T *)K, tasks, tiles);
-    else
-        hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock, kStageSlab>), grid, block, 0, st, sp,
-                           tb, (const T *)c, a0, a1, a2, (T *)M, (T *)K, tasks, tiles);
-    return hipGetLastError();
+    if (stg == kStageFull) {
+        if (sp.rows == R - 2) return launch_fwd<T, P, D, WHAT, FINAL, kStageFull, R - 2>(sp, tb, c, a, M, K, st);
+        return launch_fwd<T, P, D, WHAT, FINAL, kStageFull, R>(sp, tb, c, a, M, K, st);
+    }
+    if (stg == kStageDirect) return launch_fwd<T, P, D, WHAT, FINAL, kStageDirect, R>(sp, tb, c, a, M, K, st);
+    return launch_fwd<T, P, D, WHAT, FINAL, kStageSlab, R>(sp, tb, c, a, M, K, st);
 }
 
 template <typename T, int P, int D, int WHAT, int FINAL>
