@@ -46,12 +46,19 @@ struct Acc {
 template <>
 struct Acc<float, 1> {
     float p = 0.f, e = 0.f;
+    bool first = true;     // resolved at compile time in the unrolled loops
     __device__ __forceinline__ void add(float a, float b) {
-        float h = a * b;
-        float r = __builtin_fmaf(a, b, -h);
-        float t = p + h;
-        float z = t - p;
-        float q = (p - (t - z)) + (h - z);
+        const float h = a * b;
+        const float r = __builtin_fmaf(a, b, -h);      // a * b = h + r exactly
+        if (first) {                                   // the sum so far is h itself
+            p = h;
+            e = r;
+            first = false;
+            return;
+        }
+        const float t = p + h;                         // p + h = t + q exactly
+        const float z = t - p;
+        const float q = (p - (t - z)) + (h - z);
         p = t;
         e += q + r;
     }
@@ -159,6 +166,30 @@ __device__ __forceinline__ uint32_t block_index(int flags) {
     if (!(flags & kFlagXcdRemap)) return b;
     const uint32_t nb = gridDim.x, q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// Q consecutive staged samples from LDS (16-byte aligned when a row of Q values is a
+// multiple of 16 bytes: staged lines are runs of whole rows).
+template <typename T, int Q>
+__device__ __forceinline__ void lds_q(const T *p, T (&v)[Q]) {
+    if constexpr (Q * sizeof(T) == 16) {
+        using VT = T __attribute__((ext_vector_type(Q)));
+        const VT x = *reinterpret_cast<const VT *>(__builtin_assume_aligned(p, 16));
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = x[q];
+    } else if constexpr (Q * sizeof(T) == 32) {
+        using VT = T __attribute__((ext_vector_type(Q / 2)));
+        const VT x = *reinterpret_cast<const VT *>(__builtin_assume_aligned(p, 16));
+        const VT y = *reinterpret_cast<const VT *>(__builtin_assume_aligned(p + Q / 2, 16));
+#pragma unroll
+        for (int q = 0; q < Q / 2; ++q) {
+            v[q] = x[q];
+            v[q + Q / 2] = y[q];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = p[q];
+    }
 }
 
 // Per-wave tile context shared by the forward and adjoint bodies.
@@ -285,8 +316,7 @@ struct Forward {
                 for (int q2 = 0; q2 < Q; ++q2) {
                     T v[Q];
                     if constexpr (INLDS) {
-#pragma unroll
-                        for (int q3 = 0; q3 < Q; ++q3) v[q3] = fs[(q1 * Q + q2) * R * Q + q3];
+                        lds_q<T, Q>(fs + (q1 * Q + q2) * R * Q, v);
                     } else {
                         load_q<T, Q>(fb + ((int64_t)q1 * N2 + q2) * N3 + lo, v);
                     }
@@ -310,8 +340,7 @@ struct Forward {
             for (int q1 = 0; q1 < Q; ++q1) {
                 T v[Q];
                 if constexpr (INLDS) {
-#pragma unroll
-                    for (int q2 = 0; q2 < Q; ++q2) v[q2] = fs[q1 * R * Q + q2];
+                    lds_q<T, Q>(fs + q1 * R * Q, v);
                 } else {
                     load_q<T, Q>(fb + (int64_t)q1 * N2 + lo, v);
                 }
@@ -324,7 +353,8 @@ struct Forward {
     }
 
     // Final pass over q1 and store: X[s1][s2][sl] = sum_q1 fa[q1][s1] Va[s2][q1]
-    // (+ fb[q1][s1] Vb[s2][q1]).
+    // (+ fb[q1][s1] Vb[s2][q1]).  Slots whose column leaves the space come out as exact
+    // zeros without a test: the table factor of that column is 0 in its direction.
     //  FULL:  the whole tile (rows_here x S^d values, one contiguous range of the output)
     //         goes to LDS, shifted so that LDS and global addresses share their
     //         alignment, then leaves with 16-byte vector stores.
@@ -333,13 +363,11 @@ struct Forward {
     template <bool TWO>
     __device__ __forceinline__ void emit(cptr<FT> fa, const T (&Va)[S][Q], cptr<FT> fb, const T (&Vb)[S][Q],
                                          T *__restrict__ out) const {
-        const bool ok_last = (t.il - P + sl >= 0) && (t.il - P + sl < t.nl);
         constexpr int NS2 = (D == 3) ? S : 1;
         constexpr int VEC = 16 / (int)sizeof(T);
         const int shift = FULL ? (int)((t.row0 * SD) & (VEC - 1)) : 0;
 #pragma unroll
         for (int s1 = 0; s1 < S; ++s1) {
-            const bool ok1 = (t.i1 - P + s1 >= 0) && (t.i1 - P + s1 < sp.n[0]);
             if constexpr (FULL) {          // (the slab path's divergent copy loop forbids it)
                 fa = fresh(fa);
                 if constexpr (TWO) fb = fresh(fb);
@@ -347,8 +375,6 @@ struct Forward {
             if (t.in_tile) {
 #pragma unroll
                 for (int s2 = 0; s2 < NS2; ++s2) {
-                    bool ok = ok1 && ok_last;
-                    if constexpr (D == 3) ok = ok && (t.i2 - P + s2 >= 0) && (t.i2 - P + s2 < sp.n[1]);
                     Acc<T, FINAL> acc;
 #pragma unroll
                     for (int q1 = 0; q1 < Q; ++q1) {
@@ -357,7 +383,7 @@ struct Forward {
                             if constexpr (TWO) acc.add(fb[q1 * S + s1], Vb[s2][q1]);
                         }
                     }
-                    const T v = ok ? acc.get() : T(0);
+                    const T v = acc.get();
                     if constexpr (FULL) {
                         stage[shift + t.r * SD + s1 * SL + s2 * S + sl] = v;
                     } else if constexpr (DIRECT) {
