@@ -168,28 +168,13 @@ __device__ __forceinline__ uint32_t block_index(int flags) {
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-// Q consecutive staged samples from LDS (16-byte aligned when a row of Q values is a
-// multiple of 16 bytes: staged lines are runs of whole rows).
+// Q consecutive staged samples from LDS.  Scalar reads on purpose: the lanes of one
+// tile read R distinct rows at a time, which 16-byte reads serve with bank conflicts
+// (measured slower than pairs of 4-byte reads).
 template <typename T, int Q>
 __device__ __forceinline__ void lds_q(const T *p, T (&v)[Q]) {
-    if constexpr (Q * sizeof(T) == 16) {
-        using VT = T __attribute__((ext_vector_type(Q)));
-        const VT x = *reinterpret_cast<const VT *>(__builtin_assume_aligned(p, 16));
 #pragma unroll
-        for (int q = 0; q < Q; ++q) v[q] = x[q];
-    } else if constexpr (Q * sizeof(T) == 32) {
-        using VT = T __attribute__((ext_vector_type(Q / 2)));
-        const VT x = *reinterpret_cast<const VT *>(__builtin_assume_aligned(p, 16));
-        const VT y = *reinterpret_cast<const VT *>(__builtin_assume_aligned(p + Q / 2, 16));
-#pragma unroll
-        for (int q = 0; q < Q / 2; ++q) {
-            v[q] = x[q];
-            v[q + Q / 2] = y[q];
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) v[q] = p[q];
-    }
+    for (int q = 0; q < Q; ++q) v[q] = p[q];
 }
 
 // Per-wave tile context shared by the forward and adjoint bodies.
