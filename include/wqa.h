@@ -68,12 +68,16 @@ typedef enum wqa_dtype { WQA_F32 = 0, WQA_F64 = 1 } wqa_dtype;
 
 typedef enum wqa_kind { WQA_MASS = 0, WQA_STIFFNESS = 1 } wqa_kind;
 
-/* How the last directional contraction (over the first direction) accumulates in the
- * FP32 mode.  FP64 calls always accumulate in FP64. */
+/* How the last directional contraction (the final pass, over the first direction)
+ * accumulates in the FP32 mode; every other stage accumulates in FP32.  FP64 calls
+ * always accumulate in FP64.  Both compensated variants return the sum as if it had
+ * been computed in at least twice the working precision and rounded once. */
 typedef enum wqa_final {
-    WQA_FINAL_PLAIN = 0,        /* FP32 fused multiply-adds */
-    WQA_FINAL_COMPENSATED = 1,  /* compensated dot product (error-free products and sums) */
-    WQA_FINAL_F64 = 2           /* FP64 accumulation with the FP64 tables, rounded once */
+    WQA_FINAL_PLAIN = 0,  /* FP32 fused multiply-adds */
+    WQA_FINAL_DOT2 = 1,   /* compensated in FP32 registers: error-free products (FMA) and
+                             error-free sums, errors summed apart (Ogita, Rump, Oishi) */
+    WQA_FINAL_F64 = 2     /* compensated through an FP64 accumulator: every product of FP32
+                             values is exact in FP64, sums round at 2^-53 (default) */
 } wqa_final;
 
 /* Returns WQA_ABI_VERSION of the loaded library. */
@@ -135,8 +139,7 @@ wqa_status wqa_get_tables(const wqa_ctx *ctx, wqa_kind kind, int dir, double *ou
 wqa_status wqa_query(const wqa_ctx *ctx, int64_t *n_rows, int64_t *slots_per_row,
                      int64_t *points_per_row, int64_t *grid_dims);
 
-/* Selects how FP32 calls accumulate the last directional pass (default
- * WQA_FINAL_COMPENSATED). */
+/* Selects how FP32 calls accumulate the final directional pass (default WQA_FINAL_F64). */
 wqa_status wqa_set_final_mode(wqa_ctx *ctx, wqa_final mode);
 
 /* Mass matrix (eq:Mass with the folded coefficient c).  c: device [N_1..N_d] of dtype

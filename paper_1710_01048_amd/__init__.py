@@ -16,9 +16,9 @@ assembly via weighted Gaussian quadrature rules for B-splines" (arXiv 1710.01048
 each row i is integrated with its own weighted Gaussian rule whose weight is the
 basis function B_i (Sec. 3), one direction at a time (eq:Decompo).
 """
-from ._lib import (F32, F64, FINAL_COMPENSATED, FINAL_F64, FINAL_PLAIN, MASS, STIFFNESS,
+from ._lib import (F32, F64, FINAL_DOT2, FINAL_F64, FINAL_PLAIN, MASS, STIFFNESS,
                    WQAError, lib, lib_path)
 from .space import Space, WQAssemble
 
 __all__ = ["Space", "WQAssemble", "WQAError", "lib", "lib_path", "MASS", "STIFFNESS", "F32", "F64",
-           "FINAL_PLAIN", "FINAL_COMPENSATED", "FINAL_F64"]
+           "FINAL_PLAIN", "FINAL_DOT2", "FINAL_F64"]

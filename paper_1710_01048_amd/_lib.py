@@ -8,7 +8,7 @@ lib_path = os.path.join(_HERE, "libwqa.so")
 
 MASS, STIFFNESS = 0, 1
 F32, F64 = 0, 1
-FINAL_PLAIN, FINAL_COMPENSATED, FINAL_F64 = 0, 1, 2
+FINAL_PLAIN, FINAL_DOT2, FINAL_F64 = 0, 1, 2
 
 STATUS = {0: "WQA_OK", -1: "WQA_EINVAL", -2: "WQA_ESTATE", -3: "WQA_EUNSUPPORTED",
           -4: "WQA_ERULE", -5: "WQA_EHIP", -6: "WQA_ENOMEM"}

@@ -358,7 +358,7 @@ struct wqa_ctx {
     const float *d32[2][wqa::kMaxDim] = {};
     const double *d64[2][wqa::kMaxDim] = {};
     bool dev_current = false;
-    int final_mode = WQA_FINAL_COMPENSATED;
+    int final_mode = WQA_FINAL_F64;
 };
 
 namespace {
@@ -669,7 +669,7 @@ wqa_status wqa_query(const wqa_ctx *c, int64_t *n_rows, int64_t *slots_per_row,
 
 wqa_status wqa_set_final_mode(wqa_ctx *c, wqa_final mode) {
     if (!c) return fail(WQA_EINVAL, "wqa_set_final_mode: NULL context");
-    if (mode != WQA_FINAL_PLAIN && mode != WQA_FINAL_COMPENSATED && mode != WQA_FINAL_F64)
+    if (mode != WQA_FINAL_PLAIN && mode != WQA_FINAL_DOT2 && mode != WQA_FINAL_F64)
         return fail(WQA_EINVAL, "wqa_set_final_mode: mode %d", (int)mode);
     c->final_mode = mode;
     return ok();

@@ -33,9 +33,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // --- final-pass accumulators -------------------------------------------------------
 // FINAL 0: plain fused multiply-add in T.
-// FINAL 1: compensated dot product (Ogita, Rump and Oishi's Dot2: error-free
-//          products via FMA, error-free sums, errors summed separately) in FP32.
-// FINAL 2: FP64 accumulation, table factor taken from the FP64 table.
+// FINAL 1: compensated dot product in FP32 registers (Ogita, Rump and Oishi's Dot2:
+//          error-free products via FMA, error-free sums, errors summed separately).
+// FINAL 2: compensated through an FP64 accumulator: the FP32 factor times the FP64 table
+//          entry, summed in FP64, rounded once (a v_fma_f64 issues at the FP32 rate).
 template <typename T, int FINAL>
 struct Acc {
     T s = T(0);
@@ -796,10 +797,13 @@ __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
 
 // --- dispatch ----------------------------------------------------------------------------
 constexpr int kWavesPerBlock = 4;
+constexpr int kFwdWavesF64Full = 2;
 
 template <typename T, int P, int D, int WHAT, int FINAL, int STG, int R>
 hipError_t launch_fwd(const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a, void *M, void *K,
                       hipStream_t st) {
+    // FP64 whole-tile staging needs twice the LDS per wave: two waves per work-group
+    constexpr int kWavesPerBlock = (sizeof(T) == 8 && STG == kStageFull) ? kFwdWavesF64Full : 4;
     const int64_t nl = sp.n[D - 1];
     const int tiles = (int)((nl + R - 1) / R);
     int64_t lines = 1;
@@ -823,7 +827,7 @@ hipError_t run_forward(const DevSpace &sp, const DevTabs &tb, const void *c, con
                        void *M, void *K, hipStream_t st) {
     constexpr int S = 2 * P + 1, R = 64 / S;
     // default: FP32 whole-tile staging with vector stores; FP64 s1 slabs (LDS per wave)
-    const int stg = sp.stage >= 0 ? sp.stage : (sizeof(T) == 4 ? (int)kStageFull : (int)kStageSlab);
+    const int stg = sp.stage >= 0 ? sp.stage : (int)kStageFull;
     if (stg == kStageFull) {
         if (sp.rows == R - 2) return launch_fwd<T, P, D, WHAT, FINAL, kStageFull, R - 2>(sp, tb, c, a, M, K, st);
         return launch_fwd<T, P, D, WHAT, FINAL, kStageFull, R>(sp, tb, c, a, M, K, st);
