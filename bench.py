@@ -218,6 +218,7 @@ def main():
               "sharding note of the design document", file=sys.stderr)
         sys.exit(2)
     import paper_1710_01048_amd as wqa
+    from paper_1710_01048_amd import counts
     assert torch.cuda.is_available(), "needs a HIP device"
     dev = torch.device("cuda:0")
     if args.profile_copy:
@@ -323,6 +324,7 @@ def main():
         "roofline": roof_fwd if r32["fwd_ms"] >= r32["adj_ms"] else roof_adj,
         "roofline_by_kernel": {"forward": roof_fwd, "adjoint": roof_adj},
         "hbm_probe_torch": probe,
+        "rule_counts": counts.report(P, NEL),
     }
     if r64 is not None:
         line["fp64"] = {"forward_ms": r64["fwd_ms"], "adjoint_ms": r64["adj_ms"],

@@ -155,7 +155,7 @@ def test_config2_fused_3d_quadratic(wqa, dtype):
 
 @pytest.mark.parametrize("dtype,mode", [(torch.float64, None), (torch.float32, 1),
                                         (torch.float32, 0), (torch.float32, 2)],
-                         ids=["f64", "f32-compensated", "f32-plain", "f32-f64acc"])
+                         ids=["f64", "f32-dot2", "f32-plain", "f32-f64acc"])
 def test_config3_fused_3d_cubic_deformed(wqa, dtype, mode):
     eM, eK, eMe = _sampled_forward(wqa, 3, 3, (96, 96, 96), ("deformed",), dtype, mode)
     print(f"config3 {dtype} mode {mode}: row-scaled M {eM:.3e} K {eK:.3e}; entrywise M {eMe:.3e}")
@@ -183,6 +183,37 @@ def test_config4_adjoint_3d_cubic(wqa, dtype):
     errs += [ph.normwise_error(f[k + 1].grad.reshape(-1).cpu().numpy()[pts], wa[k]) for k in range(3)]
     print(f"config4 {dtype}: normwise gradient errors {['%.3e' % e for e in errs]}")
     assert max(errs) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_config5_forward_adjoint_160_cubed(wqa, dtype):
+    # the benchmark workload at full size, in the launch configuration the benchmark
+    # times (default rules and final pass): 160^3 cubic, Fourier c and a_k, fused forward
+    # then adjoint with G ~ N(0,1) (seeds 5001, 5002); a row sample covering every
+    # boundary class and both ragged tails of the last direction against the oracle
+    p, n_el = 3, (160, 160, 160)
+    sp = wqa.Space(3, p, n_el)
+    recipe = ("fourier", 5)
+    f = ph.device_fields(sp, recipe, dtype)
+    M, K = sp.assemble_fused(f[0], f[1:])
+    rows = st.sample_rows(list(sp.n_basis), p, 300, seed=5)
+    ridx = torch.from_numpy(rows).to(sp.device)
+    Mg, Kg = M[ridx].double().cpu().numpy(), K[ridx].double().cpu().numpy()
+    del M, K, f
+    gM = si.upstream_gradient(n_el, p, 5001, dtype, sp.device)
+    gK = si.upstream_gradient(n_el, p, 5002, dtype, sp.device)
+    dc, da = sp.adjoint(gM, gK)
+    pts = torch.from_numpy(st.point_offsets(list(sp.n_basis), p, rows).reshape(-1)).to(sp.device)
+    grads = [g.reshape(-1)[pts].double().cpu().numpy().reshape(rows.size, -1) for g in [dc] + list(da)]
+    gm, gk = gM[ridx].double().cpu().numpy(), gK[ridx].double().cpu().numpy()
+    del gM, gK, dc, da
+    torch.cuda.empty_cache()
+    Mw, Kw = ph.oracle_forward(p, n_el, rows, recipe)
+    wc, wa = oa.adjoint(p, n_el, oa.rule_tables(p, n_el), gm, gk, rows=rows)
+    eM, eK = st.row_scaled_error(Mg, Mw), st.row_scaled_error(Kg, Kw)
+    eg = max(ph.normwise_error(g, w) for g, w in zip(grads, [wc] + list(wa)))
+    print(f"config5 {dtype}: row-scaled M {eM:.3e} K {eK:.3e}; gradients normwise {eg:.3e}")
+    assert eM <= TOL[dtype] and eK <= TOL[dtype] and eg <= TOL[dtype]
 
 
 def test_config4_central_differences(wqa):
