@@ -692,22 +692,7 @@ wqa_status ready(wqa_ctx *c, const char *who, wqa_dtype dtype) {
     return WQA_OK;
 }
 
-// Tuning knobs read once from the environment: WQA_KERNEL_FLAGS (bit 0: XCD-aware
-// work-group order, bit 1: nontemporal output stores; default 0) and WQA_FWD_STAGE
-// (forward output staging 0 slab / 1 whole tile / 2 direct; default per dtype) and
-// WQA_FWD_ROWS (rows per forward wave tile: 0 = 64 / (2p+1), or two fewer).
-int env_int(const char *name, int dflt) {
-    const char *v = std::getenv(name);
-    return v && *v ? std::atoi(v) : dflt;
-}
-
 void fill(const wqa_ctx *c, wqa::DevSpace &sp, wqa::DevTabs &tb, wqa_dtype dtype) {
-    static const int flags = env_int("WQA_KERNEL_FLAGS", 0);
-    static const int stage = env_int("WQA_FWD_STAGE", -1);
-    static const int rows = env_int("WQA_FWD_ROWS", 0);
-    sp.flags = flags;
-    sp.stage = stage;
-    sp.rows = rows;
     sp.d = c->dim;
     sp.p = c->p;
     for (int k = 0; k < wqa::kMaxDim; ++k) {

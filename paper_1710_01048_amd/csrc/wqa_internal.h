@@ -11,17 +11,11 @@ constexpr int kMaxDim = 3;
 
 enum What { kWhatM = 1, kWhatK = 2, kWhatMK = 3 };
 
-// Launch-shape flags (DevSpace::flags).
-enum Flags { kFlagXcdRemap = 1, kFlagNontemporal = 2 };
-
 // Sizes of the tensor-product space as the kernels see them.
 struct DevSpace {
     int d, p;
     int64_t n[kMaxDim];   // basis functions per direction
     int64_t N[kMaxDim];   // grid points per direction (n * (p + 1))
-    int flags;            // Flags
-    int stage;            // forward output staging (-1: default for the dtype)
-    int rows;             // forward rows per wave tile (0: 64 / (2p + 1))
 };
 
 // Contraction tables T[kind][dir] laid out [n_dir][Q][S] on the device, in the call's

@@ -8,15 +8,22 @@
 //     a tile is R consecutive rows of one line, so the tables of the leading directions
 //     are uniform across the wave and the coefficient samples of neighbouring rows are
 //     neighbours in memory (row i owns grid points (i_k Q + q_k)_k, C order).
-//   * Forward: lane (r, s_d) owns one slot column s_d of row r.  It contracts its row's
-//     Q^d samples over q_d against the table column s_d, then over q_{d-1}, ... in
-//     registers, and finally over q_1 (the "final pass", selectable accumulation).
-//     Results go through a small LDS buffer, one s_1 slab at a time, so that stores
-//     to the [row][S^d] output run over consecutive addresses.
-//   * Adjoint: lane (r, q_d) owns one node column of row r.  The upstream gradient is
-//     staged through LDS one s_1 slab at a time (coalesced loads, slots outside the
-//     space zeroed), contracted over s_d, s_{d-1}, ..., and the gradient of every
-//     sample is stored directly (consecutive lanes = consecutive grid points).
+//   * Forward: lane (r, s_d) owns one slot column s_d of row r.  The tile's samples of
+//     every field are staged in LDS with wide loads; each lane contracts its row's Q^d
+//     samples over q_d against the table column s_d, then over q_{d-1}, ... in
+//     registers, and finally over q_1 (the "final pass", selectable accumulation).  The
+//     tile's whole output goes through LDS and leaves with 16-byte stores over one
+//     contiguous range of the [row][S^d] output.
+//   * Adjoint: lane (r, q_d) owns one node column of row r.  The upstream gradients
+//     stream through a ring of s_1 slabs in LDS filled by direct global-to-LDS loads
+//     (slots outside the space zeroed), are contracted over s_d, s_{d-1}, ..., and the
+//     gradient of every sample is stored directly (consecutive lanes = consecutive grid
+//     points).
+//   * The adjoint launches one kernel over the "interior" lines (every leading index at
+//     least P from both ends, so the leading tables are banded) and one over the rest,
+//     so that each kernel holds only the registers of its own code path (the interior
+//     one gains occupancy).  The forward's occupancy is set by its LDS, so it runs all
+//     lines in one launch and picks the code path per wave.
 //   * Stiffness: term k uses the stiffness table in direction k and mass tables
 //     elsewhere.  Forward terms with the mass table in direction 1 share the final
 //     pass; adjoint terms with the mass table in direction d share the first pass.
@@ -140,31 +147,13 @@ __device__ __forceinline__ constexpr bool in_band(int q, int s) {
     return s >= q && s <= q + P;
 }
 
-// Q consecutive samples starting at p (16-byte aligned when Q * sizeof(T) is a
-// multiple of 16: row points start at multiples of Q in a 16-byte aligned grid).
-template <typename T, int Q>
-__device__ __forceinline__ void load_q(const T *__restrict__ p, T (&v)[Q]) {
-    if constexpr (sizeof(T) == 4 && Q == 4) {
-        const float4 x = *reinterpret_cast<const float4 *>(p);
-        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-    } else if constexpr (sizeof(T) == 8 && Q == 4) {
-        const double2 x = *reinterpret_cast<const double2 *>(p);
-        const double2 y = *reinterpret_cast<const double2 *>(p + 2);
-        v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
-    } else {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) v[q] = p[q];
-    }
-}
-
-enum { kStageSlab = 0, kStageFull = 1, kStageDirect = 2 };
-
 // Work-group index, optionally remapped so that consecutive indices run on the same
 // XCD: the hardware deals work-groups round-robin over the 8 XCDs (each with its own
 // L2), and neighbouring tiles share the cache lines at their boundaries.
-__device__ __forceinline__ uint32_t block_index(int flags) {
+template <bool XCD>
+__device__ __forceinline__ uint32_t block_index() {
     const uint32_t b = blockIdx.x;
-    if (!(flags & kFlagXcdRemap)) return b;
+    if constexpr (!XCD) return b;
     const uint32_t nb = gridDim.x, q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
@@ -185,12 +174,43 @@ struct Tile {
     bool in_tile, active;
 };
 
-template <int D>
+// Sets of lines a launch covers: all of them, the interior ones (every leading index at
+// least P from both ends: banded tables in every leading direction) or the others.
+enum LineSet { kLinesAll = 0, kLinesInterior = 1, kLinesBoundary = 2 };
+
+// Line l of a set, enumerated in row order, as its index among all lines
+// ((i_1 n_2) + i_2 for d = 3, i_1 for d = 2).
+template <int D, int P, int LS>
+__device__ __forceinline__ int64_t line_of(const DevSpace &sp, int64_t l) {
+    if constexpr (LS == kLinesAll) return l;
+    const int64_t n0 = sp.n[0];
+    if constexpr (D == 2) {
+        if constexpr (LS == kLinesInterior) return P + l;
+        else return l < P ? l : n0 - 2 * P + l;
+    } else {
+        const int64_t n1 = sp.n[1];
+        if constexpr (LS == kLinesInterior) {
+            const int64_t w = n1 - 2 * P, a = l / w;
+            return (P + a) * n1 + P + (l - a * w);
+        } else {
+            const int64_t full = 2 * P * n1;            // i_1 among the first or last P
+            if (l < full) {
+                const int64_t a = l / n1;
+                return (a < P ? a : n0 - 2 * P + a) * n1 + (l - a * n1);
+            }
+            const int64_t r = l - full, a = r / (2 * P), b = r - a * (2 * P);
+            return (P + a) * n1 + (b < P ? b : n1 - 2 * P + b);
+        }
+    }
+}
+
+template <int D, int P, int LS>
 __device__ __forceinline__ Tile make_tile(const DevSpace &sp, int64_t task, int tiles_per_line, int R,
                                           int lanes_per_row, int lane) {
     Tile t;
-    const int64_t line = task / tiles_per_line;
-    const int tile = (int)(task - line * tiles_per_line);
+    const int64_t l = task / tiles_per_line;
+    const int tile = (int)(task - l * tiles_per_line);
+    const int64_t line = line_of<D, P, LS>(sp, l);
     t.nl = sp.n[D - 1];
     if constexpr (D == 3) {
         t.i1 = line / sp.n[1];
@@ -209,6 +229,7 @@ __device__ __forceinline__ Tile make_tile(const DevSpace &sp, int64_t task, int 
     return t;
 }
 
+// Whether every leading index of the tile's line is interior (banded leading tables).
 template <int D, int P>
 __device__ __forceinline__ bool tile_banded(const DevSpace &sp, const Tile &t) {
     bool b = t.i1 >= P && t.i1 < sp.n[0] - P;
@@ -218,9 +239,8 @@ __device__ __forceinline__ bool tile_banded(const DevSpace &sp, const Tile &t) {
 
 // --------------------------------------------------------------------------------------
 // Forward.  Lane (r, s_d): row r of the tile, slot column s_d of the last direction.
-template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R, int STG>
+template <typename T, int P, int D, int FINAL, bool BAND, int R>
 struct Forward {
-    static constexpr bool FULL = STG == kStageFull, DIRECT = STG == kStageDirect;
     static constexpr int Q = P + 1, S = 2 * P + 1;
     static constexpr int SL = (D == 3) ? S * S : S;
     static constexpr int SD = S * SL;
@@ -229,21 +249,14 @@ struct Forward {
     const DevSpace &sp;
     const DevTabs &tb;
     const Tile &t;
-    T *stage;          // this wave's staging buffer (FULL: R * S^d + 16 B, SLAB: R * S^(d-1))
+    T *stage;          // this wave's staging buffer: the tile's samples, then its output
     int lane, sl;
-    bool nt;           // nontemporal output stores
     int64_t N2, N3;
 
-    __device__ __forceinline__ void store(T *base_u, uint32_t off, T v) const {
-        if (nt) __builtin_nontemporal_store(v, base_u + off);
-        else base_u[off] = v;
-    }
-
-    // Input staging (whole-tile mode): the samples of every field the tile needs go to
-    // LDS first, each (q1[, q2]) line of the tile as one contiguous run of R rows x Q
-    // values, loaded with a few wide, non-redundant loads that are all in flight at once
-    // (in registers, the Q samples of a row would be loaded by each of its S lanes).
-    static constexpr bool INLDS = FULL;
+    // Input staging: the samples of every field the tile needs go to LDS first, each
+    // (q1[, q2]) line of the tile as one contiguous run of R rows x Q values, loaded with
+    // a few wide, non-redundant loads that are all in flight at once (in registers, the
+    // Q samples of a row would be loaded by each of its S lanes).
     static constexpr int NG = (D == 3) ? Q * Q : Q;     // lines per field
     static constexpr int FSZ = NG * R * Q;              // staged values per field
 
@@ -283,29 +296,22 @@ struct Forward {
 
     // V[s2][q1] = sum_{q2} sum_{q3} f[q1][q2][q3] t3[q3][sl] t2[q2][s2]     (d = 3)
     // V[0][q1]  = sum_{q2} f[q1][q2] t2[q2][sl]                            (d = 2)
-    // Samples come from global memory (f) or, with input staging, from field slot fi.
-    __device__ __forceinline__ void contract(const T *__restrict__ f, int fi, const T *t_last, cptr<T> t2,
-                                             T (&V)[S][Q], bool accumulate) const {
+    // Samples come from the staged field slot fi.
+    __device__ __forceinline__ void contract(int fi, const T *t_last, cptr<T> t2, T (&V)[S][Q],
+                                             bool accumulate) const {
         T tl[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) tl[q] = t_last[q * S + sl];
-        // wave-uniform part of the address, plus a 32-bit per-lane offset
-        const uint32_t lo = (uint32_t)(t.il * Q);
         const T *fs = stage + fi * FSZ + (t.r < t.rows_here ? t.r : 0) * Q;
         t2 = fresh(t2);
         if constexpr (D == 3) {
-            const T *fb = f + ((t.i1 * Q) * N2 + t.i2 * Q) * N3;
 #pragma unroll
             for (int q1 = 0; q1 < Q; ++q1) {
                 T U[Q];
 #pragma unroll
                 for (int q2 = 0; q2 < Q; ++q2) {
                     T v[Q];
-                    if constexpr (INLDS) {
-                        lds_q<T, Q>(fs + (q1 * Q + q2) * R * Q, v);
-                    } else {
-                        load_q<T, Q>(fb + ((int64_t)q1 * N2 + q2) * N3 + lo, v);
-                    }
+                    lds_q<T, Q>(fs + (q1 * Q + q2) * R * Q, v);
                     T acc = T(0);
 #pragma unroll
                     for (int q3 = 0; q3 < Q; ++q3) acc = fma(v[q3], tl[q3], acc);
@@ -321,15 +327,10 @@ struct Forward {
                 }
             }
         } else {
-            const T *fb = f + (t.i1 * Q) * N2;
 #pragma unroll
             for (int q1 = 0; q1 < Q; ++q1) {
                 T v[Q];
-                if constexpr (INLDS) {
-                    lds_q<T, Q>(fs + q1 * R * Q, v);
-                } else {
-                    load_q<T, Q>(fb + (int64_t)q1 * N2 + lo, v);
-                }
+                lds_q<T, Q>(fs + q1 * R * Q, v);
                 T acc = accumulate ? V[0][q1] : T(0);
 #pragma unroll
                 for (int q2 = 0; q2 < Q; ++q2) acc = fma(v[q2], tl[q2], acc);
@@ -340,24 +341,20 @@ struct Forward {
 
     // Final pass over q1 and store: X[s1][s2][sl] = sum_q1 fa[q1][s1] Va[s2][q1]
     // (+ fb[q1][s1] Vb[s2][q1]).  Slots whose column leaves the space come out as exact
-    // zeros without a test: the table factor of that column is 0 in its direction.
-    //  FULL:  the whole tile (rows_here x S^d values, one contiguous range of the output)
-    //         goes to LDS, shifted so that LDS and global addresses share their
-    //         alignment, then leaves with 16-byte vector stores.
-    //  SLAB:  one s1 slab at a time (rows_here runs of S^(d-1) values), scalar stores.
-    //  DIRECT: no LDS; every lane stores its own values (runs of S per row).
+    // zeros without a test: the table factor of that column is 0 in its direction.  The
+    // whole tile (rows_here x S^d values, one contiguous range of the output) goes to LDS,
+    // shifted so that LDS and global addresses share their alignment, then leaves with
+    // 16-byte stores.
     template <bool TWO>
     __device__ __forceinline__ void emit(cptr<FT> fa, const T (&Va)[S][Q], cptr<FT> fb, const T (&Vb)[S][Q],
                                          T *__restrict__ out) const {
         constexpr int NS2 = (D == 3) ? S : 1;
         constexpr int VEC = 16 / (int)sizeof(T);
-        const int shift = FULL ? (int)((t.row0 * SD) & (VEC - 1)) : 0;
+        const int shift = (int)((t.row0 * SD) & (VEC - 1));
 #pragma unroll
         for (int s1 = 0; s1 < S; ++s1) {
-            if constexpr (FULL) {          // (the slab path's divergent copy loop forbids it)
-                fa = fresh(fa);
-                if constexpr (TWO) fb = fresh(fb);
-            }
+            fa = fresh(fa);
+            if constexpr (TWO) fb = fresh(fb);
             if (t.in_tile) {
 #pragma unroll
                 for (int s2 = 0; s2 < NS2; ++s2) {
@@ -369,60 +366,36 @@ struct Forward {
                             if constexpr (TWO) acc.add(fb[q1 * S + s1], Vb[s2][q1]);
                         }
                     }
-                    const T v = acc.get();
-                    if constexpr (FULL) {
-                        stage[shift + t.r * SD + s1 * SL + s2 * S + sl] = v;
-                    } else if constexpr (DIRECT) {
-                        if (t.active) store(out + t.row0 * SD + s1 * SL + s2 * S, (uint32_t)(t.r * SD + sl), v);
-                    } else {
-                        stage[t.r * SL + s2 * S + sl] = v;
-                    }
+                    stage[shift + t.r * SD + s1 * SL + s2 * S + sl] = acc.get();
                 }
             }
-            if constexpr (STG == kStageSlab) {
-                wave_lds_sync();
-                const int n_here = t.rows_here * SL;
-                T *ob = out + t.row0 * SD + s1 * SL;
-#pragma unroll 2
-                for (int e = lane; e < n_here; e += 64) {
-                    const int rr = e / SL, tt = e - (e / SL) * SL;
-                    store(ob, (uint32_t)(rr * SD + tt), stage[e]);
-                }
-                wave_lds_sync();
-            }
         }
-        if constexpr (FULL) {
-            wave_lds_sync();
-            const int n = t.rows_here * SD;
-            T *ob = out + t.row0 * SD;
-            const int head = (VEC - shift) & (VEC - 1);
-            if (lane < head && lane < n) store(ob, (uint32_t)lane, stage[shift + lane]);
-            const int nvec = (n - head) / VEC;
-            using V = T __attribute__((ext_vector_type(VEC)));
-            for (int k = lane; k < nvec; k += 64) {
-                const int e = head + k * VEC;
-                const V v = *reinterpret_cast<const V *>(&stage[shift + e]);
-                V *dst = reinterpret_cast<V *>(ob + (uint32_t)e);
-                if (nt) __builtin_nontemporal_store(v, dst);
-                else *dst = v;
-            }
-            const int tail0 = head + nvec * VEC;
-            if (lane < n - tail0) store(ob, (uint32_t)(tail0 + lane), stage[shift + tail0 + lane]);
-            wave_lds_sync();
+        wave_lds_sync();
+        const int n = t.rows_here * SD;
+        T *ob = out + t.row0 * SD;
+        const int head = (VEC - shift) & (VEC - 1);
+        if (lane < head && lane < n) ob[lane] = stage[shift + lane];
+        const int nvec = (n - head) / VEC;
+        using V = T __attribute__((ext_vector_type(VEC)));
+        for (int k = lane; k < nvec; k += 64) {
+            const int e = head + k * VEC;
+            *reinterpret_cast<V *>(ob + (uint32_t)e) = *reinterpret_cast<const V *>(&stage[shift + e]);
         }
+        const int tail0 = head + nvec * VEC;
+        if (lane < n - tail0) ob[(uint32_t)(tail0 + lane)] = stage[shift + tail0 + lane];
+        wave_lds_sync();
     }
 };
 
-template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R, int STG>
+template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int R>
 __device__ __forceinline__ void forward_body(const DevSpace &sp, const DevTabs &tb, const Tile &t, T *stage,
                                              int lane, const T *__restrict__ cf, const T *__restrict__ a0,
                                              const T *__restrict__ a1, const T *__restrict__ a2,
                                              T *__restrict__ Mo, T *__restrict__ Ko) {
-    using F = Forward<T, P, D, FINAL, BAND, WPB, R, STG>;
+    using F = Forward<T, P, D, FINAL, BAND, R>;
     constexpr int Q = F::Q, S = F::S;
     using FT = typename F::FT;
-    F fw{sp, tb, t, stage, lane, lane - t.r * S, (sp.flags & kFlagNontemporal) != 0, sp.N[1],
-         (D == 3) ? sp.N[2] : 1};
+    F fw{sp, tb, t, stage, lane, lane - t.r * S, sp.N[1], (D == 3) ? sp.N[2] : 1};
     const int64_t rs = (int64_t)Q * S;
     cptr<T> M2 = table<T>(tb, 0, 1) + (D == 3 ? t.i2 : 0) * rs;
     cptr<T> K2 = table<T>(tb, 1, 1) + (D == 3 ? t.i2 : 0) * rs;
@@ -430,16 +403,14 @@ __device__ __forceinline__ void forward_body(const DevSpace &sp, const DevTabs &
     const T *KL = (const T *)tb.t[1][D - 1] + t.il * rs;
     cptr<FT> fM1 = final_table<T, FINAL>(tb, 0, 0) + t.i1 * rs;
     cptr<FT> fK1 = final_table<T, FINAL>(tb, 1, 0) + t.i1 * rs;
-    // Without input staging, the barriers keep each field's loads next to their use, so
-    // that the samples of only one field are live at a time (register pressure sets
-    // occupancy): the empty asm with a memory clobber stops loads from being hoisted
-    // across it, the scheduling barrier stops the machine scheduler from interleaving.
-    // With input staging every field is contracted before the first output is written
-    // (the outputs reuse the staging buffer).
+    // Every field is contracted before the first output is written (the outputs reuse the
+    // staging buffer).  The pins and phase barriers keep the phases in order: the empty
+    // asm with a memory clobber stops loads from being hoisted across it, the scheduling
+    // barrier stops the machine scheduler from interleaving.
     constexpr bool DO_M = (WHAT & kWhatM) != 0, DO_K = (WHAT & kWhatK) != 0;
     constexpr int NF = (DO_M ? 1 : 0) + (DO_K ? D : 0);
     const int fk = DO_M ? 1 : 0;                  // field slot of a_1
-    if constexpr (F::INLDS) {
+    {
         const T *fl[NF];
         if constexpr (DO_M) fl[0] = cf;
         if constexpr (DO_K) {
@@ -452,45 +423,39 @@ __device__ __forceinline__ void forward_body(const DevSpace &sp, const DevTabs &
     }
     T V[DO_M ? S : 1][Q], V1[DO_K ? S : 1][Q], V2[DO_K ? S : 1][Q];
     if constexpr (DO_M) {
-        fw.contract(cf, 0, ML, M2, V, false);
+        fw.contract(0, ML, M2, V, false);
         pin(V);
         phase_barrier();
-        if constexpr (!F::INLDS) {
-            fw.template emit<false>(fM1, V, fM1, V, Mo);
-            phase_barrier();
-        }
     }
     if constexpr (DO_K) {
         if constexpr (D == 3) {
-            fw.contract(a0, fk, ML, M2, V1, false);       // term 1: stiffness table in direction 1
+            fw.contract(fk, ML, M2, V1, false);           // term 1: stiffness table in direction 1
             pin(V1);
             phase_barrier();
-            fw.contract(a1, fk + 1, ML, K2, V2, false);   // term 2: stiffness table in direction 2
+            fw.contract(fk + 1, ML, K2, V2, false);       // term 2: stiffness table in direction 2
             pin(V2);
             phase_barrier();
-            fw.contract(a2, fk + 2, KL, M2, V2, true);    // term 3: stiffness table in direction 3
+            fw.contract(fk + 2, KL, M2, V2, true);        // term 3: stiffness table in direction 3
         } else {
-            fw.contract(a0, fk, ML, M2, V1, false);       // term 1: stiffness table in direction 1
+            fw.contract(fk, ML, M2, V1, false);           // term 1: stiffness table in direction 1
             pin(V1);
             phase_barrier();
-            fw.contract(a1, fk + 1, KL, M2, V2, false);   // term 2: stiffness table in direction 2
+            fw.contract(fk + 1, KL, M2, V2, false);       // term 2: stiffness table in direction 2
         }
         pin(V2);
         phase_barrier();
     }
-    if constexpr (F::INLDS) {
-        wave_lds_sync();                                  // every lane done reading the samples
-        if constexpr (DO_M) {
-            fw.template emit<false>(fM1, V, fM1, V, Mo);
-            phase_barrier();
-        }
+    wave_lds_sync();                                      // every lane done reading the samples
+    if constexpr (DO_M) {
+        fw.template emit<false>(fM1, V, fM1, V, Mo);
+        phase_barrier();
     }
     if constexpr (DO_K) {
         fw.template emit<true>(fK1, V1, fM1, V2, Ko);
     }
 }
 
-template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int STG, int R>
+template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int R>
 __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     DevSpace sp, DevTabs tb, const T *__restrict__ cf, const T *__restrict__ a0,
     const T *__restrict__ a1, const T *__restrict__ a2, T *__restrict__ Mo,
@@ -500,61 +465,77 @@ __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     constexpr int Q = P + 1, NG = (D == 3) ? Q * Q : Q;
     constexpr int NF = ((WHAT & kWhatM) ? 1 : 0) + ((WHAT & kWhatK) ? D : 0);
     constexpr int OUT = R * S * SL + 16 / (int)sizeof(T), IN = NF * NG * R * Q;
-    constexpr int STAGE = STG == kStageFull ? (OUT > IN ? OUT : IN) : (STG == kStageSlab ? R * SL : 1);
-    __shared__ __align__(16) T stage[WPB][STAGE];
+    __shared__ __align__(16) T stage[WPB][OUT > IN ? OUT : IN];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t task = (int64_t)block_index(sp.flags) * WPB + wave;
+    const int64_t task = (int64_t)block_index<false>() * WPB + wave;
     if (task >= n_tasks) return;                   // whole wave leaves; no block barriers below
-    const Tile t = make_tile<D>(sp, task, tiles_per_line, R, S, lane);
+    const Tile t = make_tile<D, P, kLinesAll>(sp, task, tiles_per_line, R, S, lane);
     if (tile_banded<D, P>(sp, t))
-        forward_body<T, P, D, WHAT, FINAL, true, WPB, R, STG>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
+        forward_body<T, P, D, WHAT, FINAL, true, R>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
     else
-        forward_body<T, P, D, WHAT, FINAL, false, WPB, R, STG>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
+        forward_body<T, P, D, WHAT, FINAL, false, R>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
 }
 
 // --------------------------------------------------------------------------------------
 // Adjoint.  Lane (r, q_d): row r of the tile, node column q_d of the last direction.
-// The upstream gradient of the tile is staged one s1 slab at a time (the next slab's
-// global loads are in flight while the current one is contracted); each slab reduces
-// to Z[s1][q2] in registers, and the final pass over s1 gives every output directly.
-template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R>
+// The upstream gradients of the tile stream through a ring of RING slab buffers in this
+// wave's LDS: one buffer holds one s1 slab (R rows x S^(d-1) values), filled by direct
+// global-to-LDS loads, so no registers hold the data in flight and RING - 1 slabs are on
+// their way while one is contracted.  The stream is gM's slabs, then gK's.  Each slab
+// reduces to Z[s1][q2] in registers; the final pass over s1 gives every output directly.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+// Waits until at most N vector-memory operations of this wave are in flight.  Loads
+// complete in issue order, so this waits for everything issued before the last N.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R, int RING>
 struct Adjoint {
     static constexpr int Q = P + 1, S = 2 * P + 1;
     static constexpr int SL = (D == 3) ? S * S : S;     // slots of one s1 slab
     static constexpr int SD = S * SL;
-    static constexpr int S3P = (S + 3) & ~3;            // LDS row of one (s1, s2): padded to 16 B
-    static constexpr int SLP = ((D == 3) ? S * S3P : S3P) + 4;
-    static constexpr int NPF = (R * SL + 63) / 64;      // prefetch registers per lane
+    static constexpr int U = (int)sizeof(T) / 4;        // dwords per value
+    static constexpr int NE = R * SL * U;               // dwords of one slab
+    static constexpr int NPF = (NE + 63) / 64;          // loads per lane per slab
+    static constexpr int SLOT = 64 * NPF;               // dwords per ring buffer
     static constexpr int NQ2 = (D == 3) ? Q : 1;
     using FT = typename FinalTab<T, FINAL>::type;
+    static_assert(NPF <= 32, "one validity bit per load");
+    static_assert(RING >= 2 && RING <= 4 && (RING - 1) * NPF < 64, "ring depth");
+    static constexpr bool LIMIT = sizeof(T) == 8;
 
     const DevSpace &sp;
     const Tile &t;
-    T *stage;          // R * SLP values of this wave
+    uint32_t *ring;    // RING * SLOT dwords of this wave
     int lane, ql;
+    const T *gM, *gK;
+    int s1_lo, n_s1, nM, n_tot;   // slabs per matrix, gM's slabs in the stream, all slabs
+    bool fix;                     // the tile has slots outside the space (zeroed after loading)
 
-    // Per-lane staging map of one slab, the same for every s1: element k of this lane is
-    // slot tt of tile row rr (e = lane + 64 k = rr * SL + tt); goff is its offset inside the
-    // slab's rows, loff its LDS position (padded rows), bit k of valid says whether it
-    // exists and lies inside the space (else it stages as 0).
-    struct Map {
-        uint32_t goff[NPF], loff[NPF];
-        uint32_t valid;
-    };
+    // Per-lane gather map of one slab, the same for every s1 and both matrices: dword k of
+    // this lane (d = lane + 64 k) is half d % U of value e = d / U, slot tt of tile row rr
+    // (e = rr * SL + tt); goff is its dword offset from the slab's first value.  Values
+    // outside the space or beyond the tile's rows load the slab's first value instead (an
+    // address that always exists) and have their validity bit clear.
+    uint32_t goff[NPF];
+    uint32_t valid;
 
-    __device__ __forceinline__ Map make_map() const {
-        Map m;
-        m.valid = 0;
+    __device__ __forceinline__ void make_map() {
+        valid = 0;
         const int i2 = (int)t.i2, t0 = (int)t.t0, nl = (int)t.nl, n2 = (int)sp.n[1];
 #pragma unroll
         for (int k = 0; k < NPF; ++k) {
-            const int e = lane + 64 * k;
+            const int dw = lane + 64 * k;
+            const int e = dw / U, half = dw - e * U;
             const int rr = e / SL, tt = e - rr * SL;
             const int s2 = (D == 3) ? tt / S : 0, s3 = (D == 3) ? tt - (tt / S) * S : tt;
-            m.goff[k] = (uint32_t)(rr * SD + tt);
-            m.loff[k] = (uint32_t)(rr * SLP + s2 * S3P + s3);
-            bool ok = e < t.rows_here * SL;
+            bool ok = dw < NE && rr < t.rows_here;
             if constexpr (D == 3) {
                 const int j2 = i2 - P + s2, j3 = t0 + rr - P + s3;
                 ok = ok && j2 >= 0 && j2 < n2 && j3 >= 0 && j3 < nl;
@@ -562,42 +543,71 @@ struct Adjoint {
                 const int j2 = t0 + rr - P + s3;
                 ok = ok && j2 >= 0 && j2 < nl;
             }
-            m.valid |= (ok ? 1u : 0u) << k;
+            goff[k] = ok ? (uint32_t)((rr * SD + tt) * U + half) : 0u;
+            valid |= (ok ? 1u : 0u) << k;
         }
-        pin(m.goff);
-        pin(m.loff);
-        asm volatile("" : "+v"(m.valid));
-        return m;
+        pin(goff);
+        asm volatile("" : "+v"(valid));
     }
 
-    __device__ __forceinline__ void load_slab(const T *__restrict__ g, int s1, const Map &m, T (&pf)[NPF]) const {
-        const T *gb = g + (t.row0 * SD + (int64_t)s1 * SL);       // wave-uniform
-#pragma unroll
-        for (int k = 0; k < NPF; ++k) {
-            const bool ok = (m.valid >> k) & 1u;
-            const T v = gb[ok ? m.goff[k] : 0u];                  // element 0 is always in bounds
-            pf[k] = ok ? v : T(0);
-        }
-    }
-
-    __device__ __forceinline__ void store_slab(const Map &m, const T (&pf)[NPF]) const {
+    __device__ __forceinline__ void issue(int pos) const {
+        const bool first = pos < nM;
+        const T *g = first ? gM : gK;
+        const int s1 = s1_lo + (first ? pos : pos - nM);
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(g + (t.row0 * SD + (int64_t)s1 * SL));
+        uint32_t *dst = ring + (pos % RING) * SLOT;
 #pragma unroll
         for (int k = 0; k < NPF; ++k)
-            if (64 * (k + 1) <= R * SL || lane + 64 * k < R * SL) stage[m.loff[k]] = pf[k];
+            __builtin_amdgcn_global_load_lds((glb_void_t *)(src + goff[k]), (lds_void_t *)(dst + 64 * k), 4, 0, 0);
+    }
+
+    // Waits for the slab issued `after` slabs before the newest one.
+    __device__ __forceinline__ void wait_slab(int after) const {
+        if constexpr (RING >= 4) {
+            if (after >= 3) { wait_vm<3 * NPF>(); return; }
+        }
+        if constexpr (RING >= 3) {
+            if (after >= 2) { wait_vm<2 * NPF>(); return; }
+        }
+        if (after >= 1) { wait_vm<NPF>(); return; }
+        wait_vm<0>();
+    }
+
+    // Makes slab `pos` of the stream readable: refills the buffer read last (its reads are
+    // complete) with slab pos + RING - 1, waits for slab pos and zeroes its slots outside
+    // the space.  Every lane of the wave takes part.
+    __device__ __forceinline__ const T *acquire(int pos) const {
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        if (pos + RING - 1 < n_tot) issue(pos + RING - 1);
+        const int left = n_tot - 1 - pos;
+        wait_slab(left < RING - 1 ? left : RING - 1);
+        uint32_t *slot = ring + (pos % RING) * SLOT;
+        if (fix) {
+#pragma unroll
+            for (int k = 0; k < NPF; ++k)
+                if (!((valid >> k) & 1u) && (64 * (k + 1) <= NE || lane + 64 * k < NE)) slot[64 * k + lane] = 0u;
+        }
+        wave_lds_sync();
+        return reinterpret_cast<const T *>(slot);
     }
 
     // Z[zi][q2] (+)= sum_{s2} (sum_{s3} G[s1][s2][s3] tl[s3]) t2[q2][s2] for NSET sets that
     // share the slab (tl[m], t2[m]); d = 2: Z[zi][0] = sum_{s2} G[s1][s2] tl[s2].
     template <int NSET, int NZ>
-    __device__ __forceinline__ void slab_contract(int zi, const T (&tl)[NSET][S], const cptr<T> (&t2)[NSET],
-                                                  T (&Z)[NSET][NZ][NQ2]) const {
-        const T *row = stage + (t.r < t.rows_here ? t.r : 0) * SLP;
+    __device__ __forceinline__ void slab_contract(const T *slab, int zi, const T (&tl)[NSET][S],
+                                                  const cptr<T> (&t2)[NSET], T (&Z)[NSET][NZ][NQ2]) const {
+        const T *row = slab + (t.r < t.rows_here ? t.r : 0) * SL;
         if constexpr (D == 3) {
 #pragma unroll
             for (int s2 = 0; s2 < S; ++s2) {
                 T g[S];
 #pragma unroll
-                for (int s3 = 0; s3 < S; ++s3) g[s3] = row[s2 * S3P + s3];
+                for (int s3 = 0; s3 < S; ++s3) g[s3] = row[s2 * S + s3];
+                // the table entries of one s2 at a time in scalar registers (a whole slab's
+                // would not fit beside everything else)
+                cptr<T> t2r[NSET];
+#pragma unroll
+                for (int m = 0; m < NSET; ++m) t2r[m] = fresh(t2[m]);
 #pragma unroll
                 for (int m = 0; m < NSET; ++m) {
                     T y = T(0);
@@ -605,8 +615,11 @@ struct Adjoint {
                     for (int s3 = 0; s3 < S; ++s3) y = fma(g[s3], tl[m][s3], y);
 #pragma unroll
                     for (int q2 = 0; q2 < Q; ++q2)
-                        if (!BAND || in_band<P>(q2, s2)) Z[m][zi][q2] = fma(y, t2[m][q2 * S + s2], Z[m][zi][q2]);
+                        if (!BAND || in_band<P>(q2, s2)) Z[m][zi][q2] = fma(y, t2r[m][q2 * S + s2], Z[m][zi][q2]);
                 }
+                // one s2 row of the slab at a time: the scheduler would otherwise hold the
+                // whole row of the slab in registers
+                if constexpr (LIMIT) __builtin_amdgcn_sched_barrier(0);
             }
         } else {
             T g[S];
@@ -622,12 +635,35 @@ struct Adjoint {
         }
     }
 
-    // One pass over the s1 slabs of g, then the final pass over s1 and the stores.
-    // Plain accumulation (FINAL 0, and every FP64 call) keeps running sums over s1,
-    // Q x Q per set; the FP32 compensated and FP64-accumulated passes keep the S x Q
-    // slab results Z[s1][q2] and sum them at the end.
+    // Final pass of one q1 (compensated or FP64-accumulated, s1 ascending) and its stores.
+    template <int NSET, int NZ>
+    __device__ __forceinline__ void emit_q1(int q1, const cptr<FT> (&f1)[NSET], const T (&Z)[NSET][NZ][NQ2],
+                                            T *const (&out)[NSET]) const {
+        const int64_t N2 = sp.N[1], N3 = (D == 3) ? sp.N[2] : 1;
+        const uint32_t lo = (uint32_t)(t.il * Q + ql);
+#pragma unroll
+        for (int m = 0; m < NSET; ++m) {
+            const cptr<FT> f1m = fresh(f1[m]);
+#pragma unroll
+            for (int q2 = 0; q2 < NQ2; ++q2) {
+                Acc<T, FINAL> a;
+#pragma unroll
+                for (int s1 = 0; s1 < S; ++s1)
+                    if (!BAND || in_band<P>(q1, s1)) a.add(f1m[q1 * S + s1], Z[m][s1][q2]);
+                int64_t off;     // wave-uniform part; the lane adds il * Q + ql
+                if constexpr (D == 3) off = ((t.i1 * Q + q1) * N2 + t.i2 * Q + q2) * N3;
+                else off = (t.i1 * Q + q1) * N2;
+                (out[m] + off)[lo] = a.get();
+            }
+        }
+    }
+
+    // The slabs of one matrix (stream positions pos0 ...), then the final pass over s1 and
+    // the stores.  Plain accumulation (FINAL 0, and every FP64 call) keeps running sums
+    // over s1, Q x Q per set; the FP32 compensated and FP64-accumulated passes keep the
+    // S x Q slab results Z[s1][q2] and sum them at the end.
     template <int NSET>
-    __device__ __forceinline__ void run(const T *__restrict__ g, const T (&tl)[NSET][S], const cptr<T> (&t2)[NSET],
+    __device__ __forceinline__ void run(int pos0, const T (&tl)[NSET][S], const cptr<T> (&t2)[NSET],
                                         const cptr<FT> (&f1)[NSET], T *const (&out)[NSET]) const {
         constexpr bool RUNNING = (FINAL == 0);
         constexpr int NZ = RUNNING ? 1 : S;
@@ -644,17 +680,11 @@ struct Adjoint {
 #pragma unroll
                 for (int q2 = 0; q2 < NQ2; ++q2) acc[m][z][q2] = T(0);
         }
-        const int s1_lo = (int)(t.i1 >= P ? 0 : P - t.i1);
-        const int s1_hi = (int)(sp.n[0] - 1 - t.i1 + P < S - 1 ? sp.n[0] - 1 - t.i1 + P : S - 1);
-        const Map map = make_map();
-        T pf[NPF];
-        load_slab(g, s1_lo, map, pf);
+        const int s1_hi = s1_lo + n_s1 - 1;
 #pragma unroll
         for (int s1 = 0; s1 < S; ++s1) {
             if (s1 < s1_lo || s1 > s1_hi) continue;     // slab outside the space: contributes 0
-            store_slab(map, pf);
-            wave_lds_sync();
-            if (s1 + 1 <= s1_hi) load_slab(g, s1 + 1, map, pf);
+            const T *slab = acquire(pos0 + s1 - s1_lo);
             cptr<T> t2s[NSET];
             cptr<FT> f1s[NSET];
 #pragma unroll
@@ -668,7 +698,7 @@ struct Adjoint {
                     for (int m = 0; m < NSET; ++m)
 #pragma unroll
                         for (int q2 = 0; q2 < NQ2; ++q2) Z[m][0][q2] = T(0);
-                    slab_contract<NSET, NZ>(0, tl, t2s, Z);
+                    slab_contract<NSET, NZ>(slab, 0, tl, t2s, Z);
 #pragma unroll
                     for (int m = 0; m < NSET; ++m)
 #pragma unroll
@@ -678,50 +708,67 @@ struct Adjoint {
                                 for (int q2 = 0; q2 < NQ2; ++q2)
                                     acc[m][q1][q2] = fma((T)f1s[m][q1 * S + s1], Z[m][0][q2], acc[m][q1][q2]);
                 } else {
-                    slab_contract<NSET, NZ>(s1, tl, t2s, Z);
+                    slab_contract<NSET, NZ>(slab, s1, tl, t2s, Z);
                 }
             }
-            wave_lds_sync();
+            // Banded tiles: output q1 has all its slabs once s1 = q1 + P, so it is finished
+            // and stored right away, and only P + 1 slab results stay live
+            if constexpr (BAND && !RUNNING) {
+                if (s1 >= P && t.active) emit_q1<NSET, NZ>(s1 - P, f1, Z, out);
+            }
         }
-        if (!t.active) return;
-        const int64_t N2 = sp.N[1], N3 = (D == 3) ? sp.N[2] : 1;
-        const uint32_t lo = (uint32_t)(t.il * Q + ql);
+        if constexpr (BAND && !RUNNING) return;
+        if (t.active) {
+            const int64_t N2 = sp.N[1], N3 = (D == 3) ? sp.N[2] : 1;
+            const uint32_t lo = (uint32_t)(t.il * Q + ql);
 #pragma unroll
-        for (int m = 0; m < NSET; ++m) {
-            const cptr<FT> f1m = fresh(f1[m]);
+            for (int m = 0; m < NSET; ++m) {
+                const cptr<FT> f1m = fresh(f1[m]);
 #pragma unroll
-            for (int q1 = 0; q1 < Q; ++q1)
+                for (int q1 = 0; q1 < Q; ++q1) {
 #pragma unroll
-                for (int q2 = 0; q2 < NQ2; ++q2) {
-                    T v;
-                    if constexpr (RUNNING) {
-                        v = acc[m][q1][q2];
-                    } else {
-                        Acc<T, FINAL> a;
+                    for (int q2 = 0; q2 < NQ2; ++q2) {
+                        T v;
+                        if constexpr (RUNNING) {
+                            v = acc[m][q1][q2];
+                        } else {
+                            Acc<T, FINAL> a;
 #pragma unroll
-                        for (int s1 = 0; s1 < S; ++s1)
-                            if (!BAND || in_band<P>(q1, s1)) a.add(f1m[q1 * S + s1], Z[m][s1][q2]);
-                        v = a.get();
+                            for (int s1 = 0; s1 < S; ++s1)
+                                if (!BAND || in_band<P>(q1, s1)) a.add(f1m[q1 * S + s1], Z[m][s1][q2]);
+                            v = a.get();
+                        }
+                        int64_t off;     // wave-uniform part; the lane adds il * Q + ql
+                        if constexpr (D == 3) off = ((t.i1 * Q + q1) * N2 + t.i2 * Q + q2) * N3;
+                        else off = (t.i1 * Q + q1) * N2;
+                        (out[m] + off)[lo] = v;
                     }
-                    int64_t off;     // wave-uniform part; the lane adds il * Q + ql
-                    if constexpr (D == 3) off = ((t.i1 * Q + q1) * N2 + t.i2 * Q + q2) * N3;
-                    else off = (t.i1 * Q + q1) * N2;
-                    (out[m] + off)[lo] = v;
                 }
+            }
         }
     }
 };
 
-template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R>
-__device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &tb, const Tile &t, T *stage,
+template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R, int RING>
+__device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &tb, const Tile &t, uint32_t *ring,
                                              int lane, const T *__restrict__ gM, const T *__restrict__ gK,
                                              T *__restrict__ dc, T *__restrict__ da0, T *__restrict__ da1,
                                              T *__restrict__ da2) {
-    using A = Adjoint<T, P, D, FINAL, BAND, WPB, R>;
+    using A = Adjoint<T, P, D, FINAL, BAND, WPB, R, RING>;
     constexpr int Q = A::Q, S = A::S;
     using FT = typename A::FT;
+    constexpr bool DO_M = (WHAT & kWhatM) != 0, DO_K = (WHAT & kWhatK) != 0;
     const int ql = lane - t.r * Q;
-    A adj{sp, t, stage, lane, ql};
+    const int s1_lo = (int)(t.i1 >= P ? 0 : P - t.i1);
+    const int s1_hi = (int)(sp.n[0] - 1 - t.i1 + P < S - 1 ? sp.n[0] - 1 - t.i1 + P : S - 1);
+    const int n_s1 = s1_hi - s1_lo + 1;
+    bool fix = t.t0 < P || t.t0 + t.rows_here + P > t.nl;
+    if constexpr (D == 3) fix = fix || t.i2 < P || t.i2 >= sp.n[1] - P;
+    A adj{sp, t, ring, lane, ql, gM, gK, s1_lo, n_s1, DO_M ? n_s1 : 0, (DO_M ? n_s1 : 0) + (DO_K ? n_s1 : 0), fix};
+    adj.make_map();
+#pragma unroll
+    for (int pos = 0; pos < RING - 1; ++pos)
+        if (pos < adj.n_tot) adj.issue(pos);
     const int64_t rs = (int64_t)Q * S;
     cptr<T> M2 = table<T>(tb, 0, 1) + t.i2 * rs;
     cptr<T> K2 = table<T>(tb, 1, 1) + t.i2 * rs;
@@ -735,17 +782,17 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
         tlM[s] = ML[s];
         tlK[s] = KL[s];
     }
-    if constexpr ((WHAT & kWhatM) != 0) {
+    if constexpr (DO_M) {
         T tl[1][S];
 #pragma unroll
         for (int s = 0; s < S; ++s) tl[0][s] = tlM[s];
         const cptr<T> t2[1] = {M2};
         const cptr<FT> f1[1] = {fM1};
         T *const out[1] = {dc};
-        adj.template run<1>(gM, tl, t2, f1, out);
+        adj.template run<1>(0, tl, t2, f1, out);
         phase_barrier();
     }
-    if constexpr ((WHAT & kWhatK) != 0) {
+    if constexpr (DO_K) {
         if constexpr (D == 3) {
             // term 1: (K, M, M), term 2: (M, K, M), term 3: (M, M, K) in directions (1, 2, 3)
             T tl[3][S];
@@ -758,7 +805,7 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
             const cptr<T> t2[3] = {M2, K2, M2};
             const cptr<FT> f1[3] = {fK1, fM1, fM1};
             T *const out[3] = {da0, da1, da2};
-            adj.template run<3>(gK, tl, t2, f1, out);
+            adj.template run<3>(adj.nM, tl, t2, f1, out);
         } else {
             // term 1: (K, M), term 2: (M, K) in directions (1, 2)
             T tl[2][S];
@@ -770,92 +817,94 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
             const cptr<T> t2[2] = {M2, M2};
             const cptr<FT> f1[2] = {fK1, fM1};
             T *const out[2] = {da0, da1};
-            adj.template run<2>(gK, tl, t2, f1, out);
+            adj.template run<2>(adj.nM, tl, t2, f1, out);
         }
     }
 }
 
-template <typename T, int P, int D, int WHAT, int FINAL, int WPB>
+template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int RING, bool INTERIOR>
 __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
     DevSpace sp, DevTabs tb, const T *__restrict__ gM, const T *__restrict__ gK,
     T *__restrict__ dc, T *__restrict__ da0, T *__restrict__ da1, T *__restrict__ da2,
     int64_t n_tasks, int tiles_per_line) {
     constexpr int Q = P + 1;
     constexpr int R = 64 / Q;                      // rows per wave tile
-    using A = Adjoint<T, P, D, FINAL, false, WPB, R>;
-    __shared__ __align__(16) T stage[WPB][R * A::SLP];
+    using A = Adjoint<T, P, D, FINAL, false, WPB, R, RING>;
+    __shared__ __align__(16) uint32_t ring[WPB][RING * A::SLOT];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t task = (int64_t)block_index(sp.flags) * WPB + wave;
+    const int64_t task = (int64_t)block_index<true>() * WPB + wave;
     if (task >= n_tasks) return;
-    const Tile t = make_tile<D>(sp, task, tiles_per_line, R, Q, lane);
-    if (tile_banded<D, P>(sp, t))
-        adjoint_body<T, P, D, WHAT, FINAL, true, WPB, R>(sp, tb, t, stage[wave], lane, gM, gK, dc, da0, da1, da2);
-    else
-        adjoint_body<T, P, D, WHAT, FINAL, false, WPB, R>(sp, tb, t, stage[wave], lane, gM, gK, dc, da0, da1, da2);
+    const Tile t = make_tile<D, P, INTERIOR ? kLinesInterior : kLinesBoundary>(sp, task, tiles_per_line, R, Q, lane);
+    adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING>(sp, tb, t, ring[wave], lane, gM, gK, dc, da0, da1,
+                                                              da2);
 }
 
 // --- dispatch ----------------------------------------------------------------------------
-constexpr int kWavesPerBlock = 4;
-constexpr int kFwdWavesF64Full = 2;
-
-template <typename T, int P, int D, int WHAT, int FINAL, int STG, int R>
-hipError_t launch_fwd(const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a, void *M, void *K,
-                      hipStream_t st) {
-    // FP64 whole-tile staging needs twice the LDS per wave: two waves per work-group
-    constexpr int kWavesPerBlock = (sizeof(T) == 8 && STG == kStageFull) ? kFwdWavesF64Full : 4;
-    const int64_t nl = sp.n[D - 1];
-    const int tiles = (int)((nl + R - 1) / R);
-    int64_t lines = 1;
-    for (int k = 0; k < D - 1; ++k) lines *= sp.n[k];
-    const int64_t tasks = lines * tiles;
-    const int64_t blocks = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
-    const T *a0 = nullptr, *a1 = nullptr, *a2 = nullptr;
-    if (WHAT & kWhatK) {
-        a0 = (const T *)a[0];
-        a1 = (const T *)a[1];
-        a2 = D == 3 ? (const T *)a[2] : nullptr;
+// Lines of the interior set and of the boundary set (see line_of).
+template <int D, int P>
+void line_sets(const DevSpace &sp, int64_t &interior, int64_t &boundary) {
+    int64_t all = 1, in = 1;
+    for (int k = 0; k < D - 1; ++k) {
+        all *= sp.n[k];
+        in *= sp.n[k] - 2 * P;
     }
-    hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock, STG, R>), dim3((unsigned)blocks),
-                       dim3(64 * kWavesPerBlock), 0, st, sp, tb, (const T *)c, a0, a1, a2, (T *)M, (T *)K, tasks,
-                       tiles);
-    return hipGetLastError();
+    interior = in;
+    boundary = all - in;
 }
 
 template <typename T, int P, int D, int WHAT, int FINAL>
 hipError_t run_forward(const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a,
                        void *M, void *K, hipStream_t st) {
     constexpr int S = 2 * P + 1, R = 64 / S;
-    // default: FP32 whole-tile staging with vector stores; FP64 s1 slabs (LDS per wave)
-    const int stg = sp.stage >= 0 ? sp.stage : (int)kStageFull;
-    if (stg == kStageFull) {
-        if (sp.rows == R - 2) return launch_fwd<T, P, D, WHAT, FINAL, kStageFull, R - 2>(sp, tb, c, a, M, K, st);
-        return launch_fwd<T, P, D, WHAT, FINAL, kStageFull, R>(sp, tb, c, a, M, K, st);
+    // whole-tile LDS staging: FP64 needs twice the LDS per wave, so two waves per work-group
+    constexpr int WPB = sizeof(T) == 8 ? 2 : 4;
+    const int tiles = (int)((sp.n[D - 1] + R - 1) / R);
+    int64_t lines = 1;
+    for (int k = 0; k < D - 1; ++k) lines *= sp.n[k];
+    const int64_t tasks = lines * tiles;
+    const T *a0 = nullptr, *a1 = nullptr, *a2 = nullptr;
+    if (WHAT & kWhatK) {
+        a0 = (const T *)a[0];
+        a1 = (const T *)a[1];
+        a2 = D == 3 ? (const T *)a[2] : nullptr;
     }
-    if (stg == kStageDirect) return launch_fwd<T, P, D, WHAT, FINAL, kStageDirect, R>(sp, tb, c, a, M, K, st);
-    return launch_fwd<T, P, D, WHAT, FINAL, kStageSlab, R>(sp, tb, c, a, M, K, st);
+    hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, WPB, R>), dim3((unsigned)((tasks + WPB - 1) / WPB)),
+                       dim3(64 * WPB), 0, st, sp, tb, (const T *)c, a0, a1, a2, (T *)M, (T *)K, tasks, tiles);
+    return hipGetLastError();
 }
 
 template <typename T, int P, int D, int WHAT, int FINAL>
 hipError_t run_adjoint(const DevSpace &sp, const DevTabs &tb, const void *gM, const void *gK,
                        void *dc, void *const *da, hipStream_t st) {
     constexpr int Q = P + 1, R = 64 / Q;
-    const int64_t nl = sp.n[D - 1];
-    const int tiles = (int)((nl + R - 1) / R);
-    int64_t lines = 1;
-    for (int k = 0; k < D - 1; ++k) lines *= sp.n[k];
-    const int64_t tasks = lines * tiles;
-    const int64_t blocks = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
+    // ring depth and waves per work-group: FP32 4 slabs x 4 waves, FP64 3 slabs x 2 waves
+    // (at most 64 KB of LDS per work-group either way)
+    constexpr int RING = sizeof(T) == 4 ? 4 : 3;
+    constexpr int WPB = sizeof(T) == 4 ? 4 : 2;
+    const int tiles = (int)((sp.n[D - 1] + R - 1) / R);
+    int64_t lines[2];
+    line_sets<D, P>(sp, lines[0], lines[1]);
     T *d0 = nullptr, *d1 = nullptr, *d2 = nullptr;
     if (WHAT & kWhatK) {
         d0 = (T *)da[0];
         d1 = (T *)da[1];
         d2 = D == 3 ? (T *)da[2] : nullptr;
     }
-    hipLaunchKernelGGL((adjoint_kernel<T, P, D, WHAT, FINAL, kWavesPerBlock>), dim3((unsigned)blocks),
-                       dim3(64 * kWavesPerBlock), 0, st, sp, tb, (const T *)gM, (const T *)gK, (T *)dc,
-                       d0, d1, d2, tasks, tiles);
-    return hipGetLastError();
+    for (int set = 0; set < 2; ++set) {
+        const int64_t tasks = lines[set] * tiles;
+        if (tasks == 0) continue;
+        const dim3 grid((unsigned)((tasks + WPB - 1) / WPB)), block(64 * WPB);
+        if (set == 0)
+            hipLaunchKernelGGL((adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, true>), grid, block, 0, st, sp, tb,
+                               (const T *)gM, (const T *)gK, (T *)dc, d0, d1, d2, tasks, tiles);
+        else
+            hipLaunchKernelGGL((adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, false>), grid, block, 0, st, sp,
+                               tb, (const T *)gM, (const T *)gK, (T *)dc, d0, d1, d2, tasks, tiles);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T, int P, int D, int WHAT>
