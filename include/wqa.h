@@ -166,6 +166,27 @@ wqa_status wqa_assemble_adjoint(wqa_ctx *ctx, wqa_dtype dtype, const void *gM,
                                 const void *gK, void *dc, void *const *da,
                                 void *hip_stream);
 
+/* Load vector (eq:Load): b_i = integral f B_i over the unit square or cube, with the mass
+ * rules.  Since the basis functions sum to one, f B_i = sum_j f B_i B_j, so b is the
+ * vector of row sums of the mass matrix assembled with c = f, and every row rule that is
+ * exact for M is exact here.  f: device [N_1..N_d] of dtype on the all-mass grid (like c);
+ * b: device [rows] of dtype (fully overwritten). */
+wqa_status wqa_assemble_load(wqa_ctx *ctx, wqa_dtype dtype, const void *f, void *b, void *hip_stream);
+
+/* Matrix-free product y = M x with the mass matrix of coefficient c (eq:Mass, eq:LinSys):
+ * y_i = sum_j M_ij x_j with the same rules, tables and samples as wqa_assemble_mass, but
+ * M is never formed: each row contracts the x values of its band with the tables at its
+ * own points, multiplies by c there and sums (eq:Decompo).  c as in wqa_assemble_mass;
+ * x, y: device [rows] of dtype (x is read, y fully overwritten; they must not overlap).
+ * Arithmetic is plain in the dtype (no compensated final pass). */
+wqa_status wqa_apply_mass(wqa_ctx *ctx, wqa_dtype dtype, const void *c, const void *x, void *y,
+                          void *hip_stream);
+
+/* Matrix-free product y = K x with the stiffness matrix of the diagonal coefficient a
+ * (eq:Stiffness), as wqa_apply_mass; a as in wqa_assemble_stiffness. */
+wqa_status wqa_apply_stiffness(wqa_ctx *ctx, wqa_dtype dtype, const void *const *a, const void *x,
+                               void *y, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

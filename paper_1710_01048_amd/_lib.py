@@ -23,7 +23,7 @@ class WQAError(RuntimeError):
 
 
 if not os.path.exists(lib_path):
-    raise ImportError(f"{lib_path} is missing: build it with `python -m paper_1710_01048_amd.build` "
+    raise ImportError(f"{lib_path} is missing: build it with `python paper_1710_01048_amd/build.py` "
                       "(hipcc, gfx950)")
 
 lib = ctypes.CDLL(lib_path)
@@ -49,6 +49,9 @@ _SIGS = {
     "wqa_assemble_stiffness": ([_vp, ctypes.c_int, _P(_vp), _vp, _vp], ctypes.c_int),
     "wqa_assemble_fused": ([_vp, ctypes.c_int, _vp, _P(_vp), _vp, _vp, _vp], ctypes.c_int),
     "wqa_assemble_adjoint": ([_vp, ctypes.c_int, _vp, _vp, _vp, _P(_vp), _vp], ctypes.c_int),
+    "wqa_assemble_load": ([_vp, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
+    "wqa_apply_mass": ([_vp, ctypes.c_int, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "wqa_apply_stiffness": ([_vp, ctypes.c_int, _P(_vp), _vp, _vp, _vp], ctypes.c_int),
 }
 
 for _name, (_args, _res) in _SIGS.items():

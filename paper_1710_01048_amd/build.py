@@ -1,6 +1,9 @@
 """Builds libwqa.so (host C ABI + gfx950 HIP kernels) in-tree with hipcc.
 
-    python -m paper_1710_01048_amd.build      # or: from paper_1710_01048_amd.build import build
+    python paper_1710_01048_amd/build.py [-q]
+
+Run as a script (or loaded by file path, as __graft_entry__.build() does): importing it
+through the package would load the library it is about to build.
 
 All HIP code is compiled for gfx950 only, with packed-FP32 instruction selection
 turned off (-Xclang -target-feature -Xclang -packed-fp32-ops).

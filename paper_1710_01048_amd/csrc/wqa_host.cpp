@@ -731,9 +731,45 @@ wqa_status forward(wqa_ctx *c, const char *who, wqa_dtype dtype, int what, const
     return ok();
 }
 
+wqa_status apply(wqa_ctx *c, const char *who, wqa_dtype dtype, int what, bool ones, const void *cf,
+                 const void *const *a, const void *x, void *y, void *stream) {
+    wqa_status st = ready(c, who, dtype);
+    if (st != WQA_OK) return st;
+    if (!y || (!ones && !x)) return fail(WQA_EINVAL, "%s: x and y must be non-NULL", who);
+    if (!aligned16(x) || !aligned16(y) || !aligned16(cf))
+        return fail(WQA_EINVAL, "%s: device buffers must be 16-byte aligned", who);
+    if (what == wqa::kWhatM && !cf) return fail(WQA_EINVAL, "%s: the coefficient is NULL", who);
+    if (what == wqa::kWhatK) {
+        if (!a) return fail(WQA_EINVAL, "%s: a is NULL", who);
+        for (int k = 0; k < c->dim; ++k) {
+            if (!a[k]) return fail(WQA_EINVAL, "%s: a[%d] is NULL", who, k);
+            if (!aligned16(a[k])) return fail(WQA_EINVAL, "%s: a[%d] is not 16-byte aligned", who, k);
+        }
+    }
+    wqa::DevSpace sp;
+    wqa::DevTabs tb;
+    fill(c, sp, tb, dtype);
+    hipError_t e = wqa::launch_apply((int)dtype, what, ones, sp, tb, cf, a, x, y, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(WQA_EHIP, "%s: kernel launch: %s", who, hipGetErrorString(e));
+    return ok();
+}
+
 }  // namespace
 
 extern "C" {
+
+wqa_status wqa_apply_mass(wqa_ctx *c, wqa_dtype dtype, const void *cf, const void *x, void *y, void *stream) {
+    return apply(c, "wqa_apply_mass", dtype, wqa::kWhatM, false, cf, nullptr, x, y, stream);
+}
+
+wqa_status wqa_apply_stiffness(wqa_ctx *c, wqa_dtype dtype, const void *const *a, const void *x, void *y,
+                               void *stream) {
+    return apply(c, "wqa_apply_stiffness", dtype, wqa::kWhatK, false, nullptr, a, x, y, stream);
+}
+
+wqa_status wqa_assemble_load(wqa_ctx *c, wqa_dtype dtype, const void *f, void *b, void *stream) {
+    return apply(c, "wqa_assemble_load", dtype, wqa::kWhatM, true, f, nullptr, nullptr, b, stream);
+}
 
 wqa_status wqa_assemble_mass(wqa_ctx *c, wqa_dtype dtype, const void *cf, void *M, void *stream) {
     return forward(c, "wqa_assemble_mass", dtype, wqa::kWhatM, cf, nullptr, M, nullptr, stream);

@@ -35,4 +35,9 @@ hipError_t launch_adjoint(int dtype, int final_mode, int what, const DevSpace &s
                           const DevTabs &tb, const void *gM, const void *gK,
                           void *dc, void *const *da, hipStream_t stream);
 
+// Matrix-free product y = M x (what = kWhatM, coefficient c) or y = K x (kWhatK,
+// coefficients a), or with ones = true the load vector y_i = integral c B_i (x unused).
+hipError_t launch_apply(int dtype, int what, bool ones, const DevSpace &sp, const DevTabs &tb,
+                        const void *c, const void *const *a, const void *x, void *y, hipStream_t stream);
+
 }  // namespace wqa

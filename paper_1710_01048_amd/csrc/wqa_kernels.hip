@@ -129,6 +129,11 @@ __device__ __forceinline__ void pin(T (&V)[A]) {
     for (int a = 0; a < A; ++a) asm volatile("" : "+v"(V[a]));
 }
 
+template <typename T>
+__device__ __forceinline__ void pin(T &v) {
+    asm volatile("" : "+v"(v));
+}
+
 // Makes a wave-uniform table pointer opaque at this point: table reads through it are
 // then issued after here instead of all being hoisted to the top of the kernel, which
 // would keep every table value of every phase in scalar registers at once.
@@ -840,6 +845,199 @@ __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
                                                               da2);
 }
 
+// --------------------------------------------------------------------------------------
+// Matrix-free products y = M x, y = K x and the load vector.  Lane (r, q_d) as in the
+// adjoint.  The tile's window of x (every column any of its rows reaches: i_k - P ..
+// i_k + P in each direction) is staged in LDS, zero outside the space.  Each lane
+// contracts the window over s_d, s_{d-1}, ..., s_1 into its node column -- at every point
+// of the row, sum_j T(i, q, j) x_j with the product of the directions' tables --
+// multiplies by the coefficient samples there and sums over the points; the Q lanes of
+// a row add their sums.  Summed over the points this is sum_j M_ij x_j (or K) with the
+// same rules, tables and samples as the assembled matrices, which are never stored.
+// ONES replaces x by 1 everywhere: by the partition of unity the mass product then
+// gives the load vector b_i = integral f B_i with f as the coefficient.
+template <typename T, int P, int D, bool BAND, bool ONES>
+struct Apply {
+    static constexpr int Q = P + 1, S = 2 * P + 1, R = 64 / Q;
+    static constexpr int W = R + 2 * P;                  // window length along the last direction
+    static constexpr int NQ2 = (D == 3) ? Q : 1;
+    static constexpr int NS2 = (D == 3) ? S : 1;
+
+    const DevSpace &sp;
+    const Tile &t;
+    const T *win;      // this wave's window, [s1][s2][W] (d = 3) or [s1][W]
+    int ql;
+
+    // NSET terms that share the window read: term m uses the last-direction table
+    // entries tl[ls[m]] (this lane's node ql of row il), the uniform table rows t2[m]
+    // (direction 2, d = 3) and t1[m] (direction 1), and the coefficient field f[m].
+    // Returns sum_m sum over the lane's points (q1[, q2], ql) of f[m] times the window
+    // contracted to that point.
+    template <int NSET, int NL>
+    __device__ __forceinline__ T terms(const T *const (&f)[NSET], const cptr<T> (&t1)[NSET],
+                                       const cptr<T> (&t2)[NSET], const T (&tl)[NL][S], const int (&ls)[NSET]) const {
+        T X[NSET][Q][NQ2];
+#pragma unroll
+        for (int m = 0; m < NSET; ++m)
+#pragma unroll
+            for (int q1 = 0; q1 < Q; ++q1)
+#pragma unroll
+                for (int q2 = 0; q2 < NQ2; ++q2) X[m][q1][q2] = T(0);
+        T tsum[NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            tsum[l] = T(0);
+            if constexpr (ONES) {
+#pragma unroll
+                for (int s3 = 0; s3 < S; ++s3) tsum[l] += tl[l][s3];
+            }
+        }
+        const T *row = win + (t.r < t.rows_here ? t.r : 0);
+        // s1 stays a loop: unrolled, the compiler hoists the whole window's reads and holds
+        // them in registers (the banded skip over q1 becomes a uniform branch)
+#pragma unroll 1
+        for (int s1 = 0; s1 < S; ++s1) {
+            T Z[NSET][NQ2];
+#pragma unroll
+            for (int m = 0; m < NSET; ++m)
+#pragma unroll
+                for (int q2 = 0; q2 < NQ2; ++q2) Z[m][q2] = T(0);
+#pragma unroll
+            for (int s2 = 0; s2 < NS2; ++s2) {
+                // the window row (s1, s2) of this lane's row, contracted over s3 once per
+                // last-direction table
+                T y[NL];
+                if constexpr (ONES) {
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) y[l] = tsum[l];
+                } else {
+                    T g[S];
+#pragma unroll
+                    for (int s3 = 0; s3 < S; ++s3) g[s3] = row[(s1 * NS2 + s2) * W + s3];
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        y[l] = T(0);
+#pragma unroll
+                        for (int s3 = 0; s3 < S; ++s3) y[l] = fma(g[s3], tl[l][s3], y[l]);
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < NSET; ++m) {
+                    if constexpr (D == 3) {
+#pragma unroll
+                        for (int q2 = 0; q2 < Q; ++q2)
+                            if (!BAND || in_band<P>(q2, s2)) Z[m][q2] = fma(y[ls[m]], t2[m][q2 * S + s2], Z[m][q2]);
+                    } else {
+                        Z[m][0] = y[ls[m]];
+                    }
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < NSET; ++m)
+#pragma unroll
+                for (int q1 = 0; q1 < Q; ++q1)
+                    if (!BAND || in_band<P>(q1, s1))
+#pragma unroll
+                        for (int q2 = 0; q2 < NQ2; ++q2) X[m][q1][q2] = fma(Z[m][q2], t1[m][q1 * S + s1], X[m][q1][q2]);
+        }
+        const int64_t N2 = sp.N[1], N3 = (D == 3) ? sp.N[2] : 1;
+        const uint32_t lo = (uint32_t)(t.il * Q + ql);
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < NSET; ++m)
+#pragma unroll
+            for (int q1 = 0; q1 < Q; ++q1)
+#pragma unroll
+                for (int q2 = 0; q2 < NQ2; ++q2) {
+                    int64_t off;     // wave-uniform part; the lane adds il * Q + ql
+                    if constexpr (D == 3) off = ((t.i1 * Q + q1) * N2 + t.i2 * Q + q2) * N3;
+                    else off = (t.i1 * Q + q1) * N2;
+                    acc = fma((f[m] + off)[lo], X[m][q1][q2], acc);
+                }
+        return acc;
+    }
+};
+
+template <typename T, int P, int D, int WHAT, bool ONES, bool BAND>
+__device__ __forceinline__ T apply_body(const DevSpace &sp, const DevTabs &tb, const Tile &t, const T *win, int lane,
+                                        const T *__restrict__ cf, const T *__restrict__ a0,
+                                        const T *__restrict__ a1, const T *__restrict__ a2) {
+    using A = Apply<T, P, D, BAND, ONES>;
+    constexpr int Q = A::Q, S = A::S;
+    const int ql = lane - t.r * Q;
+    const A ap{sp, t, win, ql};
+    const int64_t rs = (int64_t)Q * S;
+    cptr<T> M1 = table<T>(tb, 0, 0) + t.i1 * rs, K1 = table<T>(tb, 1, 0) + t.i1 * rs;
+    cptr<T> M2 = table<T>(tb, 0, 1) + (D == 3 ? t.i2 : 0) * rs, K2 = table<T>(tb, 1, 1) + (D == 3 ? t.i2 : 0) * rs;
+    const T *ML = (const T *)tb.t[0][D - 1] + t.il * rs + ql * S;
+    const T *KL = (const T *)tb.t[1][D - 1] + t.il * rs + ql * S;
+    if constexpr (WHAT == kWhatM) {
+        T tl[1][S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) tl[0][s] = ML[s];
+        const T *const f[1] = {cf};
+        const cptr<T> t1[1] = {M1}, t2[1] = {M2};
+        const int ls[1] = {0};
+        return ap.template terms<1, 1>(f, t1, t2, tl, ls);
+    } else {
+        T tl[2][S];      // mass and stiffness entries of the last direction
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            tl[0][s] = ML[s];
+            tl[1][s] = KL[s];
+        }
+        if constexpr (D == 3) {
+            // term k: stiffness table in direction k, mass tables elsewhere
+            const T *const f[3] = {a0, a1, a2};
+            const cptr<T> t1[3] = {K1, M1, M1}, t2[3] = {M2, K2, M2};
+            const int ls[3] = {0, 0, 1};
+            return ap.template terms<3, 2>(f, t1, t2, tl, ls);
+        } else {
+            const T *const f[2] = {a0, a1};
+            const cptr<T> t1[2] = {K1, M1}, t2[2] = {M2, M2};
+            const int ls[2] = {0, 1};
+            return ap.template terms<2, 2>(f, t1, t2, tl, ls);
+        }
+    }
+}
+
+template <typename T, int P, int D, int WHAT, bool ONES>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void apply_kernel(DevSpace sp, DevTabs tb, const T *__restrict__ cf,
+                                                    const T *__restrict__ a0, const T *__restrict__ a1,
+                                                    const T *__restrict__ a2, const T *__restrict__ x,
+                                                    T *__restrict__ y, int64_t n_tasks, int tiles_per_line) {
+    constexpr int WPB = 4, Q = P + 1, S = 2 * P + 1, R = 64 / Q;
+    constexpr int W = R + 2 * P, NL = (D == 3) ? S * S : S;
+    __shared__ __align__(16) T win[WPB][ONES ? 1 : NL * W];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t task = (int64_t)blockIdx.x * WPB + wave;
+    if (task >= n_tasks) return;
+    const Tile t = make_tile<D, P, kLinesAll>(sp, task, tiles_per_line, R, Q, lane);
+    if constexpr (!ONES) {
+        const int64_t n0 = sp.n[0], n1 = (D == 3) ? sp.n[1] : 1, nl = t.nl;
+        for (int e = lane; e < NL * W; e += 64) {
+            const int line = e / W, m = e - line * W;
+            const int s1 = (D == 3) ? line / S : line, s2 = (D == 3) ? line - (line / S) * S : 0;
+            const int64_t j1 = t.i1 - P + s1, j2 = (D == 3) ? t.i2 - P + s2 : 0, j3 = t.t0 - P + m;
+            const bool ok = j1 >= 0 && j1 < n0 && j2 >= 0 && j2 < n1 && j3 >= 0 && j3 < nl;
+            win[wave][e] = ok ? x[(j1 * n1 + j2) * nl + j3] : T(0);
+        }
+        wave_lds_sync();
+    }
+    T v;
+    if (tile_banded<D, P>(sp, t))
+        v = apply_body<T, P, D, WHAT, ONES, true>(sp, tb, t, win[wave], lane, cf, a0, a1, a2);
+    else
+        v = apply_body<T, P, D, WHAT, ONES, false>(sp, tb, t, win[wave], lane, cf, a0, a1, a2);
+    // the row's value is the sum over its Q lanes (lanes r Q .. r Q + Q - 1)
+    const int base = t.r * Q;
+    T sum = v;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) sum += __shfl(v, base + k, 64);
+    if (t.active && lane == base) y[t.row0 + t.r] = sum;
+}
+
 // --- dispatch ----------------------------------------------------------------------------
 // Lines of the interior set and of the boundary set (see line_of).
 template <int D, int P>
@@ -905,6 +1103,43 @@ hipError_t run_adjoint(const DevSpace &sp, const DevTabs &tb, const void *gM, co
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <typename T, int P, int D, int WHAT, bool ONES>
+hipError_t run_apply(const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a, const void *x,
+                     void *y, hipStream_t st) {
+    constexpr int Q = P + 1, R = 64 / Q, WPB = 4;
+    const int tiles = (int)((sp.n[D - 1] + R - 1) / R);
+    int64_t lines = 1;
+    for (int k = 0; k < D - 1; ++k) lines *= sp.n[k];
+    const int64_t tasks = lines * tiles;
+    const T *a0 = nullptr, *a1 = nullptr, *a2 = nullptr;
+    if (WHAT == kWhatK) {
+        a0 = (const T *)a[0];
+        a1 = (const T *)a[1];
+        a2 = D == 3 ? (const T *)a[2] : nullptr;
+    }
+    hipLaunchKernelGGL((apply_kernel<T, P, D, WHAT, ONES>), dim3((unsigned)((tasks + WPB - 1) / WPB)), dim3(64 * WPB),
+                       0, st, sp, tb, (const T *)c, a0, a1, a2, (const T *)x, (T *)y, tasks, tiles);
+    return hipGetLastError();
+}
+
+template <typename T, int P, int D>
+hipError_t apply_what(int what, bool ones, const DevSpace &sp, const DevTabs &tb, const void *c,
+                      const void *const *a, const void *x, void *y, hipStream_t st) {
+    if (ones) return run_apply<T, P, D, kWhatM, true>(sp, tb, c, a, x, y, st);
+    if (what == kWhatM) return run_apply<T, P, D, kWhatM, false>(sp, tb, c, a, x, y, st);
+    return run_apply<T, P, D, kWhatK, false>(sp, tb, c, a, x, y, st);
+}
+
+template <typename T>
+hipError_t apply_shape(int what, bool ones, const DevSpace &sp, const DevTabs &tb, const void *c,
+                       const void *const *a, const void *x, void *y, hipStream_t st) {
+    if (sp.p == 2 && sp.d == 2) return apply_what<T, 2, 2>(what, ones, sp, tb, c, a, x, y, st);
+    if (sp.p == 2 && sp.d == 3) return apply_what<T, 2, 3>(what, ones, sp, tb, c, a, x, y, st);
+    if (sp.p == 3 && sp.d == 2) return apply_what<T, 3, 2>(what, ones, sp, tb, c, a, x, y, st);
+    if (sp.p == 3 && sp.d == 3) return apply_what<T, 3, 3>(what, ones, sp, tb, c, a, x, y, st);
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int P, int D, int WHAT>
@@ -981,6 +1216,12 @@ hipError_t launch_forward(int dtype, int final_mode, int what, const DevSpace &s
                           const void *c, const void *const *a, void *M, void *K, hipStream_t stream) {
     if (dtype == 0) return fwd_shape<float>(final_mode, what, sp, tb, c, a, M, K, stream);
     return fwd_shape<double>(final_mode, what, sp, tb, c, a, M, K, stream);
+}
+
+hipError_t launch_apply(int dtype, int what, bool ones, const DevSpace &sp, const DevTabs &tb, const void *c,
+                        const void *const *a, const void *x, void *y, hipStream_t stream) {
+    if (dtype == 0) return apply_shape<float>(what, ones, sp, tb, c, a, x, y, stream);
+    return apply_shape<double>(what, ones, sp, tb, c, a, x, y, stream);
 }
 
 hipError_t launch_adjoint(int dtype, int final_mode, int what, const DevSpace &sp, const DevTabs &tb,

@@ -188,6 +188,47 @@ class Space:
             _stream_handle(self.device)))
         return dc, da
 
+    # --- load vector and matrix-free products -------------------------------------------
+    def _vector(self, t, name, dtype):
+        if t is None:
+            return torch.empty(self.n_rows, dtype=dtype, device=self.device)
+        if t.device != self.device or t.dtype != dtype or not t.is_contiguous() or \
+                t.numel() != self.n_rows or t.data_ptr() % 16:
+            raise ValueError(f"{name}: need contiguous, 16-byte aligned {dtype} [{self.n_rows}] on {self.device}")
+        return t
+
+    def load_vector(self, f, b=None):
+        """b_i = integral f B_i with the mass rules (f on the all-mass grid, like c)."""
+        self._need_device()
+        f = self._field(f, "f")
+        b = self._vector(b, "b", f.dtype)
+        check(lib.wqa_assemble_load(self._ctx, _DTYPES[f.dtype], ctypes.c_void_p(f.data_ptr()),
+                                    ctypes.c_void_p(b.data_ptr()), _stream_handle(self.device)))
+        return b
+
+    def apply_mass(self, c, x, y=None):
+        """y = M x without forming M (M as assemble_mass(c) would give)."""
+        self._need_device()
+        c = self._field(c, "c")
+        x = self._vector(x, "x", c.dtype)
+        y = self._vector(y, "y", c.dtype)
+        check(lib.wqa_apply_mass(self._ctx, _DTYPES[c.dtype], ctypes.c_void_p(c.data_ptr()),
+                                 ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                 _stream_handle(self.device)))
+        return y
+
+    def apply_stiffness(self, a, x, y=None):
+        """y = K x without forming K (K as assemble_stiffness(a) would give)."""
+        self._need_device()
+        a = [self._field(t, f"a[{k}]", a[0].dtype) for k, t in enumerate(a)]
+        if len(a) != self.dim:
+            raise ValueError("need one coefficient per direction")
+        x = self._vector(x, "x", a[0].dtype)
+        y = self._vector(y, "y", a[0].dtype)
+        check(lib.wqa_apply_stiffness(self._ctx, _DTYPES[a[0].dtype], self._ptrs(a), ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(y.data_ptr()), _stream_handle(self.device)))
+        return y
+
 
 class WQAssemble(torch.autograd.Function):
     """(M, K) = WQAssemble.apply(space, c, a_1, ..., a_d), differentiable in c and a_k.

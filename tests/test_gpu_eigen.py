@@ -1,0 +1,45 @@
+"""Laplace eigenvalue experiments (Sec. 4) on matrices assembled by the HIP kernels: the
+spectrum equals the one of oracle-assembled matrices, and the 10-th eigenvalue converges
+to its closed form at rate 2p in 2D and 3D."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import assembly as oa
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eig():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_1710_01048_amd import eigen
+    return eigen
+
+
+@pytest.mark.parametrize("p,n_el", [(3, (16, 16)), (2, (6, 6, 6)), (3, (5, 5, 5))])
+def test_spectrum_equals_oracle_assembly(eig, p, n_el):
+    tabs = oa.rule_tables(p, n_el)
+    ones = np.ones([(e + p) * (p + 1) for e in n_el])
+    M, K = oa.assemble(p, n_el, tabs, c=ones, a=[ones] * len(n_el))
+    want = eig.solve_laplace(M, K, [e + p for e in n_el], p, count=10)
+    got = eig.laplace_eigenvalues(len(n_el), p, n_el, count=10)
+    assert np.max(np.abs(got - want) / want) < 1e-11
+
+
+@pytest.mark.parametrize("dim,p,meshes", [(2, 2, (16, 32, 64)), (2, 3, (16, 32, 64)), (3, 2, (8, 16)),
+                                          (3, 3, (8, 16))])
+def test_tenth_eigenvalue_converges_at_rate_2p(eig, dim, p, meshes):
+    exact = eig.exact_laplace_eigenvalues(dim, 10)[9]
+    errs = []
+    for N in meshes:
+        lam = eig.laplace_eigenvalues(dim, p, (N,) * dim, count=10)
+        errs.append((lam[9] - exact) / exact)
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    print(f"d={dim} p={p} meshes {meshes}: relative errors {['%.3e' % e for e in errs]}, rates {rates}")
+    assert all(e > 0 for e in errs)
+    # 3D meshes this coarse are still slightly pre-asymptotic (rates 4.3 and 6.5 on the oracle)
+    assert abs(rates[-1] - 2 * p) < (0.3 if dim == 2 else 0.6), (errs, rates)
