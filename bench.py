@@ -163,6 +163,53 @@ def run_steps(sp, fields, gM, gK, steps, warmup):
     return {"wall_s": wall, "fwd_ms": float(np.mean(fwd)), "adj_ms": float(np.mean(adj)), "out": (M, K, dc, da)}
 
 
+def matrix_free(sp, args):
+    """Load vector and matrix-free products y = M x, y = K x on the same workload (FP32
+    and FP64): event-timed per call, with algorithmic HBM bytes per row -- the samples of
+    the fields read (Q^d each), x and y (one value each; x's band is re-read from cache)
+    -- and the floating-point work the kernel issues per row (its per-lane contraction:
+    S^2 (S + Q) + S Q^2 multiply-adds per term per node column, Q node columns)."""
+    out = {}
+    Q, S, rows = P + 1, 2 * P + 1, sp.n_rows
+    macs_term = Q * (S * S * (S + Q) + S * Q * Q + Q * Q)
+    for dtype in ((torch.float32,) if args.skip_fp64 else (torch.float32, torch.float64)):
+        b = 4 if dtype == torch.float32 else 8
+        fields, _, _ = make_inputs_fields(sp, dtype)
+        g = torch.Generator(device=sp.device)
+        g.manual_seed(5003)
+        x = torch.randn(rows, generator=g, dtype=torch.float64, device=sp.device).to(dtype)
+        y = torch.empty_like(x)
+        res = {}
+        for name, fn, nf, terms in (("load_vector", lambda: sp.load_vector(fields[0], y), 1, 0),
+                                    ("apply_mass", lambda: sp.apply_mass(fields[0], x, y), 1, 1),
+                                    ("apply_stiffness", lambda: sp.apply_stiffness(fields[1:], x, y), 3, 3)):
+            fn()
+            e0, e1 = ev(), ev()
+            e0.record()
+            for _ in range(10):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 10
+            nbytes = rows * (nf * Q ** 3 + (2 if terms else 1)) * b
+            flops = 2.0 * rows * (macs_term * terms + nf * Q ** 3)
+            res[name] = {"ms": ms, "GB_s": nbytes / (ms * 1e-3) / 1e9, "TFLOP_s": flops / (ms * 1e-3) / 1e12,
+                         "rows_per_s": rows / (ms * 1e-3)}
+        out["fp32" if b == 4 else "fp64"] = res
+        del fields, x, y
+        torch.cuda.empty_cache()
+    return out
+
+
+def make_inputs_fields(sp, dtype):
+    fields = []
+    for field in ["c", 0, 1, 2]:
+        fid = 0 if field == "c" else field + 1
+        fields.append(si.fourier_grid(sp.grid_axes(field), si.fourier_modes(CONFIG_ID, fid, 3), dtype,
+                                      sp.device).contiguous())
+    return fields, None, None
+
+
 def oracle_inputs(rows):
     from oracle import assembly as oa
     tabs = oa.rule_tables(P, NEL)
@@ -282,6 +329,9 @@ def main():
         del r64["out"], f64, gM64, gK64
         torch.cuda.empty_cache()
 
+    mfree = matrix_free(sp, args)
+    log(f"matrix-free: {mfree}")
+
     probe = hbm_probe(dev)
     log(f"hbm probe: {probe}")
 
@@ -324,6 +374,7 @@ def main():
         "roofline": roof_fwd if r32["fwd_ms"] >= r32["adj_ms"] else roof_adj,
         "roofline_by_kernel": {"forward": roof_fwd, "adjoint": roof_adj},
         "hbm_probe_torch": probe,
+        "matrix_free": mfree,
         "rule_counts": counts.report(P, NEL),
     }
     if r64 is not None:
