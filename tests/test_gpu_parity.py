@@ -294,3 +294,58 @@ def test_errors_surface(wqa):
         sp.assemble_mass(c.double(), M=torch.empty(3, device=sp.device))
     with pytest.raises(wqa.WQAError):
         sp.set_final_mode(7)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_config5_properties_every_row(wqa, dtype):
+    # 160^3 cubic in the benchmark's launch configuration, properties that hold at any
+    # size, checked on all 4.33 M rows: with c = 1 the rows of M sum to the integral of
+    # B_i (a product of (t_{i+p+1} - t_i)/(p+1) over directions) and M is symmetric; the
+    # rows of K sum to 0 for any A; the adjoint satisfies <G, M(d)> = <adjoint(G), d>
+    p, n_el = 3, (160, 160, 160)
+    sp = wqa.Space(3, p, n_el)
+    dev = sp.device
+    n = list(sp.n_basis)
+    ones = torch.ones(sp.grid_shape, dtype=dtype, device=dev)
+    a = ph.device_fields(sp, ("fourier", 5), dtype)[1:]
+    M, K = sp.assemble_fused(ones, a)
+    rows = torch.arange(sp.n_rows, device=dev)
+    idx = [rows // (n[1] * n[2]), (rows // n[2]) % n[1], rows % n[2]]
+    want = torch.ones(sp.n_rows, dtype=torch.float64, device=dev)
+    for k, e in enumerate(n_el):
+        t = torch.cat([torch.zeros(p, dtype=torch.float64), torch.arange(e + 1, dtype=torch.float64) / e,
+                       torch.ones(p, dtype=torch.float64)]).to(dev)
+        want *= (t[idx[k] + p + 1] - t[idx[k]]) / (p + 1)
+    tol = TOL[dtype]
+    rs = M.double().sum(dim=1)
+    assert ((rs - want).abs() / want).max().item() <= tol
+    Kd = K.double()
+    assert (Kd.sum(dim=1).abs() / Kd.abs().sum(dim=1)).max().item() <= tol
+    del Kd, K
+    # symmetry: slot s of row i is column j = i - p + s; its mirror slot in row j is 2p - s
+    S = 2 * p + 1
+    sl = torch.arange(S ** 3, device=dev)
+    sk = [sl // (S * S), (sl // S) % S, sl % S]
+    mirror = (S * S * (S - 1 - sk[0]) + S * (S - 1 - sk[1]) + (S - 1 - sk[2]))
+    for r0 in range(0, sp.n_rows, 1 << 19):
+        r = rows[r0:r0 + (1 << 19)]
+        ik = [x[r0:r0 + (1 << 19)] for x in idx]
+        jk = [ik[k][:, None] - p + sk[k][None, :] for k in range(3)]
+        ok = (jk[0] >= 0) & (jk[0] < n[0]) & (jk[1] >= 0) & (jk[1] < n[1]) & (jk[2] >= 0) & (jk[2] < n[2])
+        col = (jk[0] * n[1] + jk[1]) * n[2] + jk[2]
+        mine = M[r]
+        theirs = M[col.clamp(0, sp.n_rows - 1), mirror.expand_as(col)]
+        scale = mine.abs().amax(dim=1, keepdim=True).double()
+        diff = ((mine.double() - theirs.double()).abs() / scale)[ok]
+        assert diff.max().item() <= tol
+    del M
+    # dot-product identity of the adjoint (mass part), in FP64 sums
+    c = ph.device_fields(sp, ("fourier", 5), dtype)[0]
+    gM = si.upstream_gradient(n_el, p, 5001, dtype, dev)
+    Mc = sp.assemble_mass(c)
+    lhs = (gM.double() * Mc.double()).sum().item()
+    scale = (gM.double() * Mc.double()).abs().sum().item()
+    del Mc
+    dc, _ = sp.adjoint(gM, None)
+    rhs = (dc.double() * c.double()).sum().item()
+    assert abs(lhs - rhs) <= tol * scale
