@@ -35,12 +35,13 @@
 #define MAXQ (MAXP + 1)
 #define MAXS (2 * MAXP + 1)
 
-/* Open uniform knot vector on [0,1] (eq:Gmap3): p+1 zeros, k/N_el, p+1 ones. */
-static void make_knots(int p, int64_t n_el, double *t)
+/* Open knot vector on [0,1] (eq:Gmap3): p+1 zeros, the interior breakpoints, p+1 ones.
+ * breaks == NULL: uniform, k/N_el; else breaks[0..N_el] (0 = b_0 < ... < b_N = 1). */
+static void make_knots(int p, int64_t n_el, const double *breaks, double *t)
 {
     int64_t m = 0;
     for (int k = 0; k < p; ++k) t[m++] = 0.0;
-    for (int64_t k = 0; k <= n_el; ++k) t[m++] = (double)k / (double)n_el;
+    for (int64_t k = 0; k <= n_el; ++k) t[m++] = breaks ? breaks[k] : (double)k / (double)n_el;
     for (int k = 0; k < p; ++k) t[m++] = 1.0;
 }
 
@@ -93,7 +94,7 @@ static void space_free(space_t *sp)
     for (int k = 0; k < MAXD; ++k) { free(sp->knots[k]); sp->knots[k] = NULL; }
 }
 
-static int space_init(space_t *sp, int d, int p, const int64_t *n_el)
+static int space_init(space_t *sp, int d, int p, const int64_t *n_el, const double *const *brk)
 {
     memset(sp, 0, sizeof(*sp));
     if (d < 1 || d > MAXD || p < 1 || p > MAXP) return -1;
@@ -105,7 +106,7 @@ static int space_init(space_t *sp, int d, int p, const int64_t *n_el)
         sp->n_knots[k] = n_el[k] + 1 + 2 * p;
         sp->knots[k] = (double *)malloc(sizeof(double) * (size_t)sp->n_knots[k]);
         if (!sp->knots[k]) { space_free(sp); return -2; }
-        make_knots(p, n_el[k], sp->knots[k]);
+        make_knots(p, n_el[k], brk ? brk[k] : NULL, sp->knots[k]);
     }
     return 0;
 }
@@ -172,7 +173,7 @@ static int ipow(int b, int e) { int r = 1; while (e-- > 0) r *= b; return r; }
  *   M_out, K_out: [n_list][S^d] (either may be NULL).
  * Returns 0, or -1 for bad arguments, -2 when out of memory.
  */
-static int assemble_impl(int d, int p, const int64_t *n_el,
+static int assemble_impl(int d, int p, const int64_t *n_el, const double *const *brk,
                          const double *const *xM, const double *const *wM,
                          const double *const *xK, const double *const *wK,
                          const double *c, const double *const *a, int per_row,
@@ -180,7 +181,7 @@ static int assemble_impl(int d, int p, const int64_t *n_el,
                          double *M_out, double *K_out)
 {
     space_t sp;
-    int rc = space_init(&sp, d, p, n_el);
+    int rc = space_init(&sp, d, p, n_el, brk);
     if (rc) return rc;
     int64_t n_rows = 1;
     for (int k = 0; k < d; ++k) n_rows *= sp.n[k];
@@ -238,20 +239,22 @@ static int assemble_impl(int d, int p, const int64_t *n_el,
     return bad ? -1 : 0;
 }
 
-int oracle_assemble(int d, int p, const int64_t *n_el,
+/* brk: NULL (uniform knots in every direction) or per-direction breakpoints, each
+ * NULL (uniform) or breaks[0..N_el] of that direction. */
+int oracle_assemble(int d, int p, const int64_t *n_el, const double *const *brk,
                     const double *const *xM, const double *const *wM,
                     const double *const *xK, const double *const *wK,
                     const double *c, const double *const *a,
                     const int64_t *rows, int64_t n_list,
                     double *M_out, double *K_out)
 {
-    return assemble_impl(d, p, n_el, xM, wM, xK, wK, c, a, 0, rows, n_list, M_out, K_out);
+    return assemble_impl(d, p, n_el, brk, xM, wM, xK, wK, c, a, 0, rows, n_list, M_out, K_out);
 }
 
 /* Same as oracle_assemble, but the coefficients come per listed row: c[r][q] and
  * a[k][r][q] hold the samples at the Q^d points of row rows[r] (q in C order), so
  * a few rows of a very large space need no full grid on the host. */
-int oracle_assemble_rows(int d, int p, const int64_t *n_el,
+int oracle_assemble_rows(int d, int p, const int64_t *n_el, const double *const *brk,
                          const double *const *xM, const double *const *wM,
                          const double *const *xK, const double *const *wK,
                          const double *c, const double *const *a,
@@ -259,7 +262,7 @@ int oracle_assemble_rows(int d, int p, const int64_t *n_el,
                          double *M_out, double *K_out)
 {
     if (!rows) return -1;
-    return assemble_impl(d, p, n_el, xM, wM, xK, wK, c, a, 1, rows, n_list, M_out, K_out);
+    return assemble_impl(d, p, n_el, brk, xM, wM, xK, wK, c, a, 1, rows, n_list, M_out, K_out);
 }
 
 /*
@@ -270,7 +273,7 @@ int oracle_assemble_rows(int d, int p, const int64_t *n_el,
  * outside the space are ignored.  Either side may be NULL (its outputs are then not
  * written).  Returns 0, -1 for bad arguments, -2 when out of memory.
  */
-int oracle_adjoint(int d, int p, const int64_t *n_el,
+int oracle_adjoint(int d, int p, const int64_t *n_el, const double *const *brk,
                    const double *const *xM, const double *const *wM,
                    const double *const *xK, const double *const *wK,
                    const int64_t *rows, int64_t n_list,
@@ -278,7 +281,7 @@ int oracle_adjoint(int d, int p, const int64_t *n_el,
                    double *dc, double *const *da)
 {
     space_t sp;
-    int rc = space_init(&sp, d, p, n_el);
+    int rc = space_init(&sp, d, p, n_el, brk);
     if (rc) return rc;
     int64_t n_rows = 1;
     for (int k = 0; k < d; ++k) n_rows *= sp.n[k];

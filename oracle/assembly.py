@@ -41,7 +41,7 @@ def _lib():
     lib = ctypes.CDLL(_LIB)
     P = ctypes.POINTER
     dpp = P(P(ctypes.c_double))
-    lib.oracle_assemble.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_int64),
+    lib.oracle_assemble.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_int64), dpp,
                                     dpp, dpp, dpp, dpp,
                                     P(ctypes.c_double), dpp,
                                     P(ctypes.c_int64), ctypes.c_int64,
@@ -49,7 +49,7 @@ def _lib():
     lib.oracle_assemble.restype = ctypes.c_int
     lib.oracle_assemble_rows.argtypes = lib.oracle_assemble.argtypes
     lib.oracle_assemble_rows.restype = ctypes.c_int
-    lib.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_int64),
+    lib.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_int64), dpp,
                                    dpp, dpp, dpp, dpp,
                                    P(ctypes.c_int64), ctypes.c_int64,
                                    P(ctypes.c_double), P(ctypes.c_double),
@@ -68,18 +68,47 @@ def _direction(p, n_el, kind):
     return x, w
 
 
-def rule_tables(p, n_el):
+def rule_tables(p, n_el, breaks=None):
     """Per-direction rule tables for elements counts n_el (tuple, one per direction):
-    dict with lists xM, wM, xK, wK of flat float64 arrays [n_k * (p+1)]."""
-    out = {"xM": [], "wM": [], "xK": [], "wK": []}
-    for ne in n_el:
-        x, w = _direction(p, int(ne), "mass")
-        out["xM"].append(x)
-        out["wM"].append(w)
-        x, w = _direction(p, int(ne), "stiffness")
-        out["xK"].append(x)
-        out["wK"].append(w)
+    dict with lists xM, wM, xK, wK of flat float64 arrays [n_k * (p+1)], and "breaks"
+    (per direction None for uniform knots, else the breakpoints).  breaks: None, or a
+    list with one entry per direction, None (uniform) or breakpoints 0 = b_0 < ... < b_N
+    = 1 whose rules come from ``oracle.nonuniform`` (homotopy from the uniform rules)."""
+    out = {"xM": [], "wM": [], "xK": [], "wK": [], "breaks": []}
+    for k, ne in enumerate(n_el):
+        b = None if breaks is None else breaks[k]
+        for kind, kx, kw in (("mass", "xM", "wM"), ("stiffness", "xK", "wK")):
+            if b is None:
+                x, w = _direction(p, int(ne), kind)
+            else:
+                x, w = _direction_breaks(p, tuple(float(v) for v in b), kind)
+            out[kx].append(x)
+            out[kw].append(w)
+        out["breaks"].append(None if b is None else np.ascontiguousarray(np.asarray(b, dtype=np.float64)))
     return out
+
+
+@functools.lru_cache(maxsize=None)
+def _direction_breaks(p, breaks, kind):
+    from . import nonuniform
+    xs, ws = nonuniform.direction_table(p, breaks, kind)
+    x = np.ascontiguousarray(np.array(xs, dtype=np.float64).reshape(-1))
+    w = np.ascontiguousarray(np.array(ws, dtype=np.float64).reshape(-1))
+    x.setflags(write=False)
+    w.setflags(write=False)
+    return x, w
+
+
+def _breaks_ptr(tables, keep):
+    brk = tables.get("breaks")
+    if brk is None or all(b is None for b in brk):
+        return None
+    arr = (ctypes.POINTER(ctypes.c_double) * len(brk))()
+    for k, b in enumerate(brk):
+        if b is not None:
+            arr[k] = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            keep.append(b)
+    return arr
 
 
 def grid_axes(tables, field):
@@ -126,8 +155,9 @@ def assemble(p, n_el, tables, c=None, a=None, rows=None, per_row=False):
     keep += [xM, wM, xK, wK]
     P = ctypes.POINTER(ctypes.c_double)
     fn = lib.oracle_assemble_rows if per_row else lib.oracle_assemble
+    brk = _breaks_ptr(tables, keep)
     rc = fn(
-        d, p, ne.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), xM, wM, xK, wK,
+        d, p, ne.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), brk, xM, wM, xK, wK,
         None if c64 is None else c64.ctypes.data_as(P),
         None if a64 is None else _ptr_array(a64),
         None if rows_arr is None else rows_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
@@ -157,8 +187,10 @@ def adjoint(p, n_el, tables, gM=None, gK=None, rows=None):
     da = [np.empty((n_list, QD)) for _ in range(d)] if gK is not None else None
     xM, wM = _ptr_array(tables["xM"]), _ptr_array(tables["wM"])
     xK, wK = _ptr_array(tables["xK"]), _ptr_array(tables["wK"])
+    keep = [xM, wM, xK, wK]
+    brk = _breaks_ptr(tables, keep)
     rc = lib.oracle_adjoint(
-        d, p, ne.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), xM, wM, xK, wK,
+        d, p, ne.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), brk, xM, wM, xK, wK,
         None if rows_arr is None else rows_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
         n_list,
         None if gM64 is None else gM64.ctypes.data_as(P),
