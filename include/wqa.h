@@ -100,6 +100,15 @@ void wqa_destroy(wqa_ctx *ctx);
  * (eq:Gmap3).  Discards any rules set before. */
 wqa_status wqa_set_space(wqa_ctx *ctx, int dim, int degree, const int64_t *n_elem);
 
+/* Sets the knots of direction dir to the open knot vector with breakpoints
+ * breaks[0..n_elem[dir]] (0 = b_0 < b_1 < ... < b_N = 1; p+1 fold ends, simple interior
+ * knots, eq:Gmap3), or back to uniform when breaks is NULL.  Discards that direction's
+ * rules; wqa_set_default_rules then traces every row's rule from the uniform one by
+ * homotopy continuation of the knots (the approach the paper names for its future work,
+ * Sec. 1 and Conclusion), and wqa_set_rules validates against these knots.  WQA_EINVAL
+ * for breakpoints that do not run from 0 to 1 or are not strictly increasing. */
+wqa_status wqa_set_knots(wqa_ctx *ctx, int dir, const double *breaks);
+
 /* Installs the default rules for both kinds in every direction: the paper's
  * interior rules (eq:WQquadratic, eq:WQcubic, eq:WQquadraticStiff, eq:WQcubicStiff),
  * solved on the host by Newton (x87 extended precision, rounded once to FP64) from
@@ -107,7 +116,12 @@ wqa_status wqa_set_space(wqa_ctx *ctx, int dim, int degree, const int64_t *n_ele
  * every interior row; and, for the p rows at each end that the paper leaves open
  * (Remark closing Sec. 3.2), weighted Gaussian rules of at most p+1 nodes solved the
  * same way (exactness on the row's interacting functions, completed by degree-
- * elevation monomials), padded to Q nodes with zero weights. */
+ * elevation monomials), padded to Q nodes with zero weights.  On a direction with
+ * breakpoints (wqa_set_knots) each row's rule is traced from that uniform rule along
+ * the straight path of the knots; the free parameter that symmetry fixes on uniform
+ * knots is fixed by the condition symmetry leaves in the elements' own coordinates.
+ * WQA_ERULE when a path meets a singular point (a stiffness node reaching the zero of
+ * B'_j, where its weight diverges): there is no rule of this family on those knots. */
 wqa_status wqa_set_default_rules(wqa_ctx *ctx);
 
 /* Installs a caller's rule for one kind and direction: nodes[n_dir*q] in [0, 1] and

@@ -39,6 +39,7 @@ _SIGS = {
     "wqa_create": ([_P(_vp), ctypes.c_int], ctypes.c_int),
     "wqa_destroy": ([_vp], None),
     "wqa_set_space": ([_vp, ctypes.c_int, ctypes.c_int, _i64p], ctypes.c_int),
+    "wqa_set_knots": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
     "wqa_set_default_rules": ([_vp], ctypes.c_int),
     "wqa_set_rules": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_double], ctypes.c_int),
     "wqa_get_rules": ([_vp, ctypes.c_int, ctypes.c_int, _dp, _dp], ctypes.c_int),

@@ -1,11 +1,14 @@
 // Host side of libwqa: the C ABI declared in include/wqa.h.
 //
 // Responsibilities (all setup, none of it on the timed path):
-//   * the spline space: open uniform knots per direction (Sec. 2.2, eq:Gmap3, eq:DimUni);
+//   * the spline space: open knots per direction, uniform by default or with given
+//     breakpoints (Sec. 2.2, eq:Gmap3, eq:DimUni);
 //   * the weighted Gaussian rules: Newton in FP64 on the exactness conditions
 //     (eq:GaussQuadSys / eq:GaussQuadSysStiff) for the paper's interior rules
 //     (Sec. 3.1.1, 3.1.2, 3.2.1, 3.2.2) and for the boundary rows the paper leaves
-//     open (Remark closing Sec. 3.2);
+//     open (Remark closing Sec. 3.2); on non-uniform knots, the same rules traced from
+//     the uniform ones by homotopy continuation of the knot vector (the approach the
+//     paper names for its future work, Sec. 1 and Conclusion);
 //   * validation of caller-supplied rules (exactness against element-wise
 //     Gauss-Legendre integrals, nodes inside the support and off the knots);
 //   * contraction tables T[j][q][s] = w * phi_j(x) * phi_{j-p+s}(x) per direction and
@@ -21,6 +24,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -50,21 +54,24 @@ wqa_status ok() {
 using real = long double;
 constexpr real PI = 3.141592653589793238462643383279502884L;
 
-// B-splines on an open uniform knot vector in element units: knot t_i = clamp(i - p,
-// 0, nel).  Cox-de Boor with right-continuous degree-0 pieces, the last interval
-// closed at the right end.
+// B-splines on an open knot vector in element units: knot t_i = b[clamp(i - p, 0, nel)]
+// with breakpoints b (b_e = e for uniform knots, b == nullptr).  Cox-de Boor with
+// right-continuous degree-0 pieces, the last interval closed at the right end.
 struct Knots {
     int p;
     int64_t nel;
+    const real *b = nullptr;      // nel + 1 breakpoints in element units, or nullptr: uniform
     real t(int64_t i) const {
         int64_t v = i - p;
-        return (real)(v < 0 ? 0 : (v > nel ? nel : v));
+        v = v < 0 ? 0 : (v > nel ? nel : v);
+        return b ? b[v] : (real)v;
     }
+    real brk(int64_t e) const { return t(e + p); }      // left end of element e
 };
 
 real bspline(const Knots &kn, int64_t i, int deg, real u) {
     real v[8];
-    const real last = (real)kn.nel;
+    const real last = kn.brk(kn.nel);
     for (int k = 0; k <= deg; ++k) {
         real a = kn.t(i + k), b = kn.t(i + k + 1);
         bool in = (a <= u && u < b) || (u == last && b == last && a < b);
@@ -129,15 +136,18 @@ void gauss_legendre(int m, std::vector<real> &x, std::vector<real> &w) {
     }
 }
 
-// Integral over integer elements [lo, hi) of f (element units), exact for piecewise
-// polynomials of degree <= 2m - 1 with integer breakpoints.
+// Integral of f (element units) over elements lo .. hi-1 of the knots, m-point
+// Gauss-Legendre per element: exact for piecewise polynomials of degree <= 2m - 1 with
+// breakpoints at the knots.
 template <class F>
-real integrate(F f, int64_t lo, int64_t hi, int m) {
+real integrate(F f, const Knots &kn, int64_t lo, int64_t hi, int m) {
     std::vector<real> gx, gw;
     gauss_legendre(m, gx, gw);
     real s = 0.0;
-    for (int64_t e = lo; e < hi; ++e)
-        for (int k = 0; k < m; ++k) s += gw[k] * f((real)e + gx[k]);
+    for (int64_t e = lo; e < hi; ++e) {
+        const real a = kn.brk(e), L = kn.brk(e + 1) - a;
+        for (int k = 0; k < m; ++k) s += gw[k] * L * f(a + L * gx[k]);
+    }
     return s;
 }
 
@@ -229,7 +239,7 @@ bool solve_interior(int p, int kind, LocalRule &out) {
     // exactness against columns j, j+1, ..., j+nu-1 (the mirrored columns follow by symmetry)
     std::vector<real> exact(nu);
     for (int o = 0; o < nu; ++o)
-        exact[o] = integrate([&](real u) { return phi(kn, kind, j + o, u) * phi(kn, kind, j, u); },
+        exact[o] = integrate([&](real u) { return phi(kn, kind, j + o, u) * phi(kn, kind, j, u); }, kn,
                              base, j + 1, p + 2);
     auto residual = [&](const std::vector<real> &v, std::vector<real> &f) {
         LocalRule r;
@@ -299,7 +309,7 @@ bool solve_boundary(int p, int kind, int j, LocalRule &out) {
     };
     std::vector<real> exact(m);
     for (int t = 0; t < m; ++t)
-        exact[t] = integrate([&](real u) { return test(t, u) * phi(kn, kind, j, u); }, 0, j + 1, p + 3);
+        exact[t] = integrate([&](real u) { return test(t, u) * phi(kn, kind, j, u); }, kn, 0, j + 1, p + 3);
     auto residual = [&](const std::vector<real> &v, std::vector<real> &f) {
         for (int t = 0; t < m; ++t) {
             real s = 0.0;
@@ -338,6 +348,175 @@ bool solve_boundary(int p, int kind, int j, LocalRule &out) {
     return false;
 }
 
+// ---------------------------------------------------------------------------------
+// Rules on non-uniform knots.  Each row's rule is traced from its uniform rule along the
+// straight path of the breakpoints, b(lam) = (1 - lam) b_uniform + lam b_target (element
+// units, uniform b_e = e), with Newton at every step starting from the previous root.
+// On uniform knots the interior rules fix their free parameter by symmetry; off them,
+// the condition symmetry leaves in each element's own coordinate
+// r = (x - b_e) / (b_{e+1} - b_e) of the node's element takes its place:
+//   quadratic mass: the middle node at r = 1/2 (the paper's tau_2 = 3/2);
+//   cubic mass and stiffness: r(first node) + r(last node) = 1; cubic stiffness also
+//     keeps omega_1 equal to the length of the support's first element (1 on uniform
+//     knots, the paper's choice);
+//   quadratic stiffness: the middle node at the zero of B'_j in the middle element
+//     (3/2 on uniform knots), with the printed weight 8/9 (it multiplies 0).
+// Boundary rows keep their square systems with the actual knots (the extra functions
+// are truncated powers at the first distinct knots from the clamped end).  A path that
+// runs into a singular point (a stiffness node meeting the zero of B'_j, where its weight
+// diverges) has no rule of this family at its end: the solver reports failure.
+struct RowSystem {
+    int p, kind;
+    int64_t j, n;
+    bool interior;
+    int nn = 0;                                  // boundary rows: node count
+    Knots kn{0, 0, nullptr};
+    real mid = 0;                                // quadratic stiffness: the middle node
+    std::vector<std::function<real(real)>> tests;
+    std::vector<real> exact;
+
+    RowSystem(int p_, int kind_, int64_t j_, int64_t n_)
+        : p(p_), kind(kind_), j(j_), n(n_), interior(j_ >= p_ && j_ < n_ - p_) {}
+
+    real lo(int q) const { return kn.t(j + q); }          // left end of support element q
+    real rel(int q, real x) const { return (x - lo(q)) / (lo(q + 1) - lo(q)); }
+
+    void setup(const Knots &k) {
+        kn = k;
+        tests.clear();
+        auto column = [this](int64_t i) { return [this, i](real u) { return phi(kn, kind, i, u); }; };
+        if (interior) {
+            const int64_t last = (kind == WQA_MASS) ? j + p : j + p - 1;   // sum_i B'_i = 0 drops one
+            for (int64_t i = j - p; i <= last; ++i) tests.push_back(column(i));
+            if (kind == WQA_STIFFNESS && p == 2) {
+                const real a = lo(1), b = lo(2);                  // B'_j is linear there
+                const real da = phi(kn, kind, j, a), db = phi(kn, kind, j, b);
+                mid = a + da * (b - a) / (da - db);
+            }
+        } else {
+            const bool left = j < p;
+            int extra = 0;
+            boundary_shape(p, kind, (int)(left ? j : n - 1 - j), nn, extra);
+            const int deg = (kind == WQA_MASS) ? p : p - 1;
+            int64_t first = left ? 0 : j - p, last = left ? j + p : n - 1;
+            if (kind == WQA_STIFFNESS) {
+                if (left) --last;
+                else ++first;
+            }
+            for (int64_t i = first; i <= last; ++i) tests.push_back(column(i));
+            for (int k2 = 0; k2 < extra; ++k2) {
+                if (left) {
+                    const real t = kn.brk(k2);
+                    tests.push_back([t, deg](real u) { return u > t ? std::pow(u - t, (real)(deg + 1)) : (real)0; });
+                } else {
+                    const real t = kn.brk(kn.nel - k2);
+                    tests.push_back([t, deg](real u) { return u < t ? std::pow(t - u, (real)(deg + 1)) : (real)0; });
+                }
+            }
+        }
+        exact.assign(tests.size(), 0);
+        const int64_t e_lo = std::max<int64_t>(0, j - p), e_hi = std::min<int64_t>(kn.nel, j + 1);
+        for (size_t t = 0; t < tests.size(); ++t)
+            exact[t] = integrate([&](real u) { return tests[t](u) * phi(kn, kind, j, u); }, kn, e_lo, e_hi, 2 * p + 2);
+    }
+
+    void expand(const std::vector<real> &v, std::vector<real> &tau, std::vector<real> &om) const {
+        if (!interior) {
+            tau.assign(v.begin(), v.begin() + nn);
+            om.assign(v.begin() + nn, v.end());
+        } else if (kind == WQA_MASS && p == 2) {
+            tau = {v[0], (lo(1) + lo(2)) / 2, v[1]};
+            om = {v[2], v[3], v[4]};
+        } else if (kind == WQA_MASS) {
+            tau.assign(v.begin(), v.begin() + 4);
+            om.assign(v.begin() + 4, v.end());
+        } else if (p == 2) {
+            tau = {v[0], mid, v[1]};
+            om = {v[2], (real)8 / 9, v[3]};
+        } else {
+            tau.assign(v.begin(), v.begin() + 4);
+            om = {lo(1) - lo(0), v[4], v[5], v[6]};
+        }
+    }
+
+    std::vector<real> unknowns(const std::vector<real> &tau, const std::vector<real> &om) const {
+        if (!interior || (kind == WQA_MASS && p == 3)) {
+            std::vector<real> v(tau);
+            v.insert(v.end(), om.begin(), om.end());
+            return v;
+        }
+        if (kind == WQA_MASS) return {tau[0], tau[2], om[0], om[1], om[2]};
+        if (p == 2) return {tau[0], tau[2], om[0], om[2]};
+        return {tau[0], tau[1], tau[2], tau[3], om[1], om[2], om[3]};
+    }
+
+    void residual(const std::vector<real> &v, std::vector<real> &f) const {
+        std::vector<real> tau, om;
+        expand(v, tau, om);
+        f.assign(v.size(), 0);
+        for (size_t t = 0; t < tests.size(); ++t) {
+            real sum = 0;
+            for (size_t q = 0; q < tau.size(); ++q) sum += om[q] * phi(kn, kind, j, tau[q]) * tests[t](tau[q]);
+            f[t] = sum - exact[t];
+        }
+        if (interior && p == 3) f[tests.size()] = rel(0, tau[0]) + rel(3, tau[3]) - 1;
+    }
+
+    bool admissible(const std::vector<real> &v) const {
+        std::vector<real> tau, om;
+        expand(v, tau, om);
+        for (real w : om)
+            if (!(w > 0)) return false;
+        if (interior) {
+            for (int q = 0; q <= p; ++q)
+                if (!(tau[q] > lo(q) && tau[q] < lo(q + 1))) return false;
+            if (p == 3 && kind == WQA_STIFFNESS && !(tau[0] < (lo(0) + lo(1)) / 2)) return false;
+            return true;
+        }
+        const real a = kn.t(j), b = kn.t(j + p + 1);
+        for (size_t q = 0; q < tau.size(); ++q) {
+            if (!(tau[q] > a && tau[q] < b)) return false;
+            if (q + 1 < tau.size() && !(tau[q] < tau[q + 1])) return false;
+            for (int64_t e = std::max<int64_t>(0, j - p); e <= std::min<int64_t>(kn.nel - 1, j); ++e) {
+                const real ea = kn.brk(e), eb = kn.brk(e + 1), tiny = (real)1e-8 * (eb - ea);
+                if (std::fabs(tau[q] - ea) < tiny || std::fabs(tau[q] - eb) < tiny) return false;
+            }
+        }
+        return true;
+    }
+};
+
+// Traces row j's rule (element units, unpadded) from the uniform one to the knots with
+// breakpoints `target` (element units, nel + 1 values).
+bool trace_row(int p, int kind, int64_t j, int64_t nel, const std::vector<real> &target, const LocalRule &uniform,
+               LocalRule &out) {
+    RowSystem rs(p, kind, j, nel + p);
+    std::vector<real> br(nel + 1);
+    auto knots_at = [&](real lam) {
+        for (int64_t e = 0; e <= nel; ++e) br[e] = (1 - lam) * (real)e + lam * target[e];
+        return Knots{p, nel, br.data()};
+    };
+    auto res = [&](const std::vector<real> &v, std::vector<real> &f) { rs.residual(v, f); };
+    rs.setup(knots_at(0));
+    std::vector<real> v = rs.unknowns(uniform.tau, uniform.omega);
+    real lam = 0, step = (real)0.25;
+    while (lam < 1) {
+        const real nxt = std::min((real)1, lam + step);
+        rs.setup(knots_at(nxt));
+        std::vector<real> w = v;
+        if (newton(res, w, (real)1e-17L) && rs.admissible(w)) {
+            v = w;
+            lam = nxt;
+            step = std::min(step * 2, (real)0.25);
+        } else {
+            step /= 2;
+            if (step < (real)1 / 4096) return false;
+        }
+    }
+    rs.expand(v, out.tau, out.omega);
+    return true;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------
@@ -348,6 +527,7 @@ struct wqa_ctx {
     int64_t nel[wqa::kMaxDim] = {0, 0, 0};
     int64_t n[wqa::kMaxDim] = {0, 0, 0};
     int64_t N[wqa::kMaxDim] = {0, 0, 0};
+    std::vector<real> brk[wqa::kMaxDim];      // breakpoints in element units; empty: uniform
     std::vector<double> nodes[2][wqa::kMaxDim], omega[2][wqa::kMaxDim];
     std::vector<double> tab64[2][wqa::kMaxDim];
     std::vector<float> tab32[2][wqa::kMaxDim];
@@ -364,6 +544,10 @@ struct wqa_ctx {
 namespace {
 
 int Q_of(const wqa_ctx *c) { return c->p + 1; }
+
+Knots knots_of(const wqa_ctx *c, int dir) {
+    return Knots{c->p, c->nel[dir], c->brk[dir].empty() ? nullptr : c->brk[dir].data()};
+}
 int S_of(const wqa_ctx *c) { return 2 * c->p + 1; }
 
 bool rules_complete(const wqa_ctx *c) {
@@ -377,7 +561,7 @@ bool rules_complete(const wqa_ctx *c) {
 void build_table(wqa_ctx *c, int kind, int dir) {
     const int p = c->p, Q = Q_of(c), S = S_of(c);
     const int64_t n = c->n[dir], nel = c->nel[dir];
-    const Knots kn{p, nel};
+    const Knots kn = knots_of(c, dir);
     std::vector<double> &T = c->tab64[kind][dir];
     T.assign((size_t)n * Q * S, 0.0);
     const real scale = (kind == WQA_MASS) ? (real)1 : (real)nel * (real)nel;
@@ -442,9 +626,10 @@ wqa_status upload(wqa_ctx *c) {
 wqa_status validate(const wqa_ctx *c, int kind, int dir, const double *x, const double *w, double tol) {
     const int p = c->p, Q = Q_of(c);
     const int64_t n = c->n[dir], nel = c->nel[dir];
-    const Knots kn{p, nel};
+    const Knots kn = knots_of(c, dir);
     for (int64_t j = 0; j < n; ++j) {
         const real lo = kn.t(j), hi = kn.t(j + p + 1);
+        const int64_t e_lo = std::max<int64_t>(0, j - p), e_hi = std::min<int64_t>(nel, j + 1);   // support elements
         for (int q = 0; q < Q; ++q) {
             double xv = x[j * Q + q], wv = w[j * Q + q];
             if (!std::isfinite(xv) || !std::isfinite(wv) || xv < 0.0 || xv > 1.0)
@@ -455,14 +640,17 @@ wqa_status validate(const wqa_ctx *c, int kind, int dir, const double *x, const 
             if (!(u > lo && u < hi))
                 return fail(WQA_ERULE, "row %lld node %d at %.17g lies outside the support [%g, %g] (element units)",
                             (long long)j, q, (double)u, (double)lo, (double)hi);
-            if (std::fabs(u - std::nearbyint(u)) < 1e-9L)
-                return fail(WQA_ERULE, "row %lld node %d at %.17g sits on a knot", (long long)j, q, (double)u);
+            for (int64_t e = e_lo; e < e_hi; ++e) {
+                const real a = kn.brk(e), b = kn.brk(e + 1), tiny = (real)1e-9 * (b - a);
+                if (std::fabs(u - a) < tiny || std::fabs(u - b) < tiny)
+                    return fail(WQA_ERULE, "row %lld node %d at %.17g sits on a knot", (long long)j, q, (double)u);
+            }
         }
         if (tol < 0) continue;
         real worst = 0, scale = 0;
         for (int64_t i = std::max<int64_t>(0, j - p); i <= std::min<int64_t>(n - 1, j + p); ++i) {
-            real exact = integrate([&](real u) { return phi(kn, kind, i, u) * phi(kn, kind, j, u); },
-                                   (int64_t)lo, (int64_t)hi, p + 2);
+            real exact = integrate([&](real u) { return phi(kn, kind, i, u) * phi(kn, kind, j, u); }, kn,
+                                   e_lo, e_hi, p + 2);
             real quad = 0;
             for (int q = 0; q < Q; ++q) {
                 real u = (real)x[j * Q + q] * (real)nel;
@@ -524,6 +712,48 @@ wqa_status default_direction(wqa_ctx *c, const LocalRule &interior, const std::v
     return WQA_OK;
 }
 
+// Default rule of one direction on non-uniform knots: every row traced from its uniform
+// rule (interior: the cardinal rule translated; boundary: the boundary rules, mirrored
+// on the right), padded like the uniform rules.
+wqa_status homotopy_direction(wqa_ctx *c, int kind, const LocalRule &interior, const std::vector<LocalRule> &boundary,
+                              int dir, std::vector<double> &x, std::vector<double> &w) {
+    const int p = c->p, Q = Q_of(c);
+    const int64_t n = c->n[dir], nel = c->nel[dir];
+    const real fn = (real)nel;
+    const Knots kn = knots_of(c, dir);
+    x.assign((size_t)n * Q, 0.0);
+    w.assign((size_t)n * Q, 0.0);
+    for (int64_t j = 0; j < n; ++j) {
+        LocalRule uni, r;
+        if (j >= p && j < n - p) {
+            for (int q = 0; q < Q; ++q) {
+                uni.tau.push_back((real)(j - p) + interior.tau[q]);
+                uni.omega.push_back(interior.omega[q]);
+            }
+        } else if (j < p) {
+            uni = boundary[j];
+        } else {
+            const LocalRule &b = boundary[n - 1 - j];
+            const int m = (int)b.tau.size();
+            for (int q = 0; q < m; ++q) {
+                uni.tau.push_back(fn - b.tau[m - 1 - q]);
+                uni.omega.push_back(b.omega[m - 1 - q]);
+            }
+        }
+        if (!trace_row(p, kind, j, nel, c->brk[dir], uni, r))
+            return fail(WQA_ERULE, "%s rule of direction %d, row %lld: the homotopy from the uniform rule met a "
+                        "singular point (no rule of this family on these knots)",
+                        kind == WQA_MASS ? "mass" : "stiffness", dir, (long long)j);
+        const real pad = j < p ? (kn.brk(0) + kn.brk(1)) / 2 : (kn.brk(nel - 1) + kn.brk(nel)) / 2;
+        for (int q = 0; q < Q; ++q) {
+            const bool real_node = q < (int)r.tau.size();
+            x[j * Q + q] = (double)((real_node ? r.tau[q] : pad) / fn);
+            w[j * Q + q] = real_node ? (double)(r.omega[q] / fn) : 0.0;
+        }
+    }
+    return WQA_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------
@@ -578,6 +808,7 @@ wqa_status wqa_set_space(wqa_ctx *c, int dim, int degree, const int64_t *n_elem)
         c->nel[k] = k < dim ? n_elem[k] : 0;
         c->n[k] = k < dim ? n_elem[k] + degree : 0;
         c->N[k] = c->n[k] * (degree + 1);
+        c->brk[k].clear();
         for (int r = 0; r < 2; ++r) {
             c->have_rule[r][k] = false;
             c->nodes[r][k].clear();
@@ -587,6 +818,34 @@ wqa_status wqa_set_space(wqa_ctx *c, int dim, int degree, const int64_t *n_elem)
         }
     }
     c->have_space = true;
+    c->dev_current = false;
+    return ok();
+}
+
+wqa_status wqa_set_knots(wqa_ctx *c, int dir, const double *breaks) {
+    if (!c) return fail(WQA_EINVAL, "wqa_set_knots: NULL context");
+    if (!c->have_space) return fail(WQA_ESTATE, "wqa_set_knots: call wqa_set_space first");
+    if (dir < 0 || dir >= c->dim) return fail(WQA_EINVAL, "wqa_set_knots: dir %d of %d", dir, c->dim);
+    const int64_t nel = c->nel[dir];
+    std::vector<real> b;
+    if (breaks) {
+        if (breaks[0] != 0.0 || breaks[nel] != 1.0)
+            return fail(WQA_EINVAL, "wqa_set_knots: breakpoints must run from 0 to 1 (got %g .. %g)", breaks[0],
+                        breaks[nel]);
+        for (int64_t e = 0; e < nel; ++e)
+            if (!std::isfinite(breaks[e + 1]) || !(breaks[e + 1] - breaks[e] > 1e-12))
+                return fail(WQA_EINVAL, "wqa_set_knots: breakpoints not strictly increasing at %lld", (long long)e);
+        b.resize(nel + 1);
+        for (int64_t e = 0; e <= nel; ++e) b[e] = (real)breaks[e] * (real)nel;
+    }
+    c->brk[dir] = b;
+    for (int r = 0; r < 2; ++r) {
+        c->have_rule[r][dir] = false;
+        c->nodes[r][dir].clear();
+        c->omega[r][dir].clear();
+        c->tab64[r][dir].clear();
+        c->tab32[r][dir].clear();
+    }
     c->dev_current = false;
     return ok();
 }
@@ -606,7 +865,12 @@ wqa_status wqa_set_default_rules(wqa_ctx *c) {
                             kind ? "stiffness" : "mass", c->p, j);
         for (int k = 0; k < c->dim; ++k) {
             std::vector<double> x, w;
-            default_direction(c, interior, boundary, k, x, w);
+            if (c->brk[k].empty()) {
+                default_direction(c, interior, boundary, k, x, w);
+            } else {
+                wqa_status st = homotopy_direction(c, kind, interior, boundary, k, x, w);
+                if (st != WQA_OK) return st;
+            }
             wqa_status st = validate(c, kind, k, x.data(), w.data(), 1e-12);
             if (st != WQA_OK) return st;
             st = install(c, kind, k, x.data(), w.data());

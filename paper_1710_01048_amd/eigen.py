@@ -72,13 +72,14 @@ def solve_laplace(M_band, K_band, n_basis, degree, count=10):
     return np.sort(w)
 
 
-def laplace_eigenvalues(dim, degree, n_elem, count=10, device="cuda:0"):
+def laplace_eigenvalues(dim, degree, n_elem, count=10, device="cuda:0", breaks=None):
     """Assemble M (c = 1) and K (A = I) in FP64 with the library's kernels on `device` and
-    return the `count` smallest Dirichlet eigenvalues."""
+    return the `count` smallest Dirichlet eigenvalues.  breaks: as for ``Space`` (None:
+    uniform knots)."""
     import torch
 
     from .space import Space
-    sp = Space(dim, degree, n_elem, device=device)
+    sp = Space(dim, degree, n_elem, device=device, breaks=breaks)
     ones = torch.ones(sp.grid_shape, dtype=torch.float64, device=sp.device)
     M, K = sp.assemble_fused(ones, [ones] * dim)
     return solve_laplace(M.cpu().numpy(), K.cpu().numpy(), sp.n_basis, degree, count)

@@ -23,10 +23,12 @@ class Space:
 
     device: a torch CUDA (HIP) device, or None for a host-only space (rules and tables
     only; the assemble calls then fail).  rules: "default" installs the library's
-    rules; None leaves them to ``set_rules``.
+    rules; None leaves them to ``set_rules``.  breaks: None (uniform knots), or one
+    entry per direction, None or the breakpoints 0 = b_0 < ... < b_N = 1 of that
+    direction (the default rules are then traced from the uniform ones by homotopy).
     """
 
-    def __init__(self, dim, degree, n_elem, device="cuda:0", rules="default"):
+    def __init__(self, dim, degree, n_elem, device="cuda:0", rules="default", breaks=None):
         self.dim, self.degree = int(dim), int(degree)
         self.n_elem = tuple(int(e) for e in n_elem)
         if len(self.n_elem) != self.dim:
@@ -38,6 +40,19 @@ class Space:
         self._ctx = handle
         ne = (ctypes.c_int64 * self.dim)(*self.n_elem)
         check(lib.wqa_set_space(self._ctx, self.dim, self.degree, ne))
+        self.breaks = [None] * self.dim
+        if breaks is not None:
+            if len(breaks) != self.dim:
+                raise ValueError("breaks needs one entry per direction")
+            dp = ctypes.POINTER(ctypes.c_double)
+            for k, b in enumerate(breaks):
+                if b is None:
+                    continue
+                arr = np.ascontiguousarray(np.asarray(b, dtype=np.float64))
+                if arr.shape != (self.n_elem[k] + 1,):
+                    raise ValueError(f"breaks[{k}] needs n_elem[{k}] + 1 = {self.n_elem[k] + 1} values")
+                check(lib.wqa_set_knots(self._ctx, k, arr.ctypes.data_as(dp)))
+                self.breaks[k] = arr
         if rules == "default":
             check(lib.wqa_set_default_rules(self._ctx))
         elif rules is not None:
