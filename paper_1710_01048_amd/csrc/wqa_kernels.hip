@@ -375,19 +375,26 @@ struct Forward {
                 }
             }
         }
+        // FP32 streams the output past the caches with nontemporal stores (it is not read
+        // again here; measured 2-7% faster); FP64 measured faster with ordinary stores.
+        constexpr bool NT = sizeof(T) == 4;
+        using V = T __attribute__((ext_vector_type(VEC)));
+        auto put = [](auto v, auto *dst) {
+            if constexpr (NT) __builtin_nontemporal_store(v, dst);
+            else *dst = v;
+        };
         wave_lds_sync();
         const int n = t.rows_here * SD;
         T *ob = out + t.row0 * SD;
         const int head = (VEC - shift) & (VEC - 1);
-        if (lane < head && lane < n) ob[lane] = stage[shift + lane];
+        if (lane < head && lane < n) put(stage[shift + lane], ob + lane);
         const int nvec = (n - head) / VEC;
-        using V = T __attribute__((ext_vector_type(VEC)));
         for (int k = lane; k < nvec; k += 64) {
             const int e = head + k * VEC;
-            *reinterpret_cast<V *>(ob + (uint32_t)e) = *reinterpret_cast<const V *>(&stage[shift + e]);
+            put(*reinterpret_cast<const V *>(&stage[shift + e]), reinterpret_cast<V *>(ob + (uint32_t)e));
         }
         const int tail0 = head + nvec * VEC;
-        if (lane < n - tail0) ob[(uint32_t)(tail0 + lane)] = stage[shift + tail0 + lane];
+        if (lane < n - tail0) put(stage[shift + tail0 + lane], ob + (uint32_t)(tail0 + lane));
         wave_lds_sync();
     }
 };
