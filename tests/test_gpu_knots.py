@@ -69,3 +69,23 @@ def test_graded_mesh_eigenvalues_converge_at_rate_2p(wqa, p):
     print(f"graded 2D p={p}: relative errors {['%.3e' % e for e in errs]}, rates {rates}")
     assert all(e > 0 for e in errs)
     assert abs(rates[-1] - 2 * p) < 0.35, (errs, rates)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_products_and_load_vector_on_nonuniform_knots(wqa, dtype):
+    from test_gpu_apply import _product_error
+    d, p, n_el, meshes = CASES[2]
+    breaks = [None if m is None else MESHES[m] for m in meshes]
+    sp = wqa.Space(d, p, n_el, breaks=breaks)
+    tabs = oa.rule_tables(p, n_el, breaks)
+    fields = ph._random_fields(p, n_el, 23)
+    f = [torch.from_numpy(v).to(sp.device, dtype) for v in fields]
+    Mw, Kw = oa.assemble(p, n_el, tabs, c=fields[0], a=fields[1:])
+    cols = st.columns([e + p for e in n_el], p, np.arange(sp.n_rows))
+    x = np.random.default_rng(29).standard_normal(sp.n_rows)
+    xd = torch.from_numpy(x).to(sp.device, dtype)
+    x = xd.double().cpu().numpy()
+    eM = _product_error(sp.apply_mass(f[0], xd).cpu().numpy(), Mw, cols, x)
+    eK = _product_error(sp.apply_stiffness(f[1:], xd).cpu().numpy(), Kw, cols, x)
+    eb = _product_error(sp.load_vector(f[0]).cpu().numpy(), Mw, cols, np.ones_like(x))
+    assert max(eM, eK, eb) <= TOL[dtype]
