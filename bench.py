@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time of the cpu_baseline sample")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-modes", action="store_true", help="time only the headline final pass")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="leave out the other workloads (matrix-free products, 96^3 forward): profiler runs")
     ap.add_argument("--profile-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -356,10 +358,12 @@ def main():
         del r64["out"], f64, gM64, gK64
         torch.cuda.empty_cache()
 
-    mfree = matrix_free(sp, args)
-    log(f"matrix-free: {mfree}")
-    cube96 = deformed_cube_forward(wqa, dev)
-    log(f"96^3 deformed cube forward: {cube96}")
+    mfree, cube96 = None, None
+    if not args.headline_only:
+        mfree = matrix_free(sp, args)
+        log(f"matrix-free: {mfree}")
+        cube96 = deformed_cube_forward(wqa, dev)
+        log(f"96^3 deformed cube forward: {cube96}")
 
     probe = hbm_probe(dev)
     log(f"hbm probe: {probe}")
