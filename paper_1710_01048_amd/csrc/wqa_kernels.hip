@@ -163,6 +163,18 @@ __device__ __forceinline__ uint32_t block_index() {
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Work-group index remapped in runs of 8·G: within a run, XCD x takes the G consecutive
+// indices x·G .. x·G+G-1, which it receives G dispatches apart.  Neighbouring tiles then
+// share an L2 while the whole chip still sweeps one contiguous window of tiles (unlike
+// block_index<true>, which gives each XCD its own eighth of the grid).  The incomplete
+// last run keeps the identity, so the map is a permutation of [0, gridDim.x).
+template <int G>
+__device__ __forceinline__ uint32_t block_grouped() {
+    const uint32_t b = blockIdx.x, span = 8u * G, full = gridDim.x / span * span;
+    if (b >= full) return b;
+    return b - b % span + (b % 8) * G + (b / 8) % G;
+}
+
 // Q consecutive staged samples from LDS.  Scalar reads on purpose: the lanes of one
 // tile read R distinct rows at a time, which 16-byte reads serve with bank conflicts
 // (measured slower than pairs of 4-byte reads).
@@ -480,7 +492,7 @@ __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     __shared__ __align__(16) T stage[WPB][OUT > IN ? OUT : IN];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t task = (int64_t)block_index<false>() * WPB + wave;
+    const int64_t task = (int64_t)block_grouped<8>() * WPB + wave;
     if (task >= n_tasks) return;                   // whole wave leaves; no block barriers below
     const Tile t = make_tile<D, P, kLinesAll>(sp, task, tiles_per_line, R, S, lane);
     if (tile_banded<D, P>(sp, t))
