@@ -505,8 +505,9 @@ __global__ __launch_bounds__(64 * WPB) void forward_kernel(
 // Adjoint.  Lane (r, q_d): row r of the tile, node column q_d of the last direction.
 // The upstream gradients of the tile stream through a ring of RING slab buffers in this
 // wave's LDS: one buffer holds one s1 slab (R rows x S^(d-1) values), filled by direct
-// global-to-LDS loads, so no registers hold the data in flight and RING - 1 slabs are on
-// their way while one is contracted.  The stream is gM's slabs, then gK's.  Each slab
+// global-to-LDS loads, so no registers hold the data in flight.  Slab pos + RING - 1 is
+// issued when slab pos is taken up, and every load of the wave is then complete before
+// slab pos is read (see acquire()).  The stream is gM's slabs, then gK's.  Each slab
 // reduces to Z[s1][q2] in registers; the final pass over s1 gives every output directly.
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
@@ -517,6 +518,63 @@ template <int N>
 __device__ __forceinline__ void wait_vm() {
     static_assert(N >= 0 && N < 64, "vmcnt range");
     asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// S consecutive values of a ring slab (LDS byte address a, aligned to the value size),
+// read in one asm block that also waits for them.  The compiler treats any LDS read as
+// possibly aliasing a pending direct-to-LDS load and puts its own vmcnt(0) wait before it;
+// acquire() places that wait itself, and these reads keep the compiler from adding more.
+template <typename T, int S>
+__device__ __forceinline__ void lds_row(uint32_t a, T (&g)[S]) {
+    static_assert(S == 5 || S == 7, "rows of 2p+1 values, p = 2 or 3");
+    using T2 = T __attribute__((ext_vector_type(2)));
+    T2 x0, x1, x2;
+    T x3;
+    if constexpr (sizeof(T) == 4 && S == 7) {
+        asm volatile(
+            "ds_read2_b32 %0, %4 offset1:1\n\t"
+            "ds_read2_b32 %1, %4 offset0:2 offset1:3\n\t"
+            "ds_read2_b32 %2, %4 offset0:4 offset1:5\n\t"
+            "ds_read_b32 %3, %4 offset:24\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(x0), "=&v"(x1), "=&v"(x2), "=&v"(x3) : "v"(a) : "memory");
+    } else if constexpr (sizeof(T) == 4) {
+        asm volatile(
+            "ds_read2_b32 %0, %3 offset1:1\n\t"
+            "ds_read2_b32 %1, %3 offset0:2 offset1:3\n\t"
+            "ds_read_b32 %2, %3 offset:16\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(x0), "=&v"(x1), "=&v"(x3) : "v"(a) : "memory");
+    } else if constexpr (S == 7) {
+        asm volatile(
+            "ds_read2_b64 %0, %4 offset1:1\n\t"
+            "ds_read2_b64 %1, %4 offset0:2 offset1:3\n\t"
+            "ds_read2_b64 %2, %4 offset0:4 offset1:5\n\t"
+            "ds_read_b64 %3, %4 offset:48\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(x0), "=&v"(x1), "=&v"(x2), "=&v"(x3) : "v"(a) : "memory");
+    } else {
+        asm volatile(
+            "ds_read2_b64 %0, %3 offset1:1\n\t"
+            "ds_read2_b64 %1, %3 offset0:2 offset1:3\n\t"
+            "ds_read_b64 %2, %3 offset:32\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(x0), "=&v"(x1), "=&v"(x3) : "v"(a) : "memory");
+    }
+    g[0] = x0.x;
+    g[1] = x0.y;
+    g[2] = x1.x;
+    g[3] = x1.y;
+    if constexpr (S == 7) {
+        g[4] = x2.x;
+        g[5] = x2.y;
+    }
+    g[S - 1] = x3;
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t lds_addr(const T *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) T *)p;
 }
 
 template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R, int RING>
@@ -599,7 +657,10 @@ struct Adjoint {
 
     // Makes slab `pos` of the stream readable: refills the buffer read last (its reads are
     // complete) with slab pos + RING - 1, waits for slab pos and zeroes its slots outside
-    // the space.  Every lane of the wave takes part.
+    // the space, then waits for every load of the wave.  The last wait keeps no slab in
+    // flight while this one is contracted: in same-process A/B runs at 160^3 that was 6%
+    // faster in FP32 (3% in FP64) than waiting for slab pos alone, and 2% faster than
+    // waiting for everything before issuing the next slab.  Every lane takes part.
     __device__ __forceinline__ const T *acquire(int pos) const {
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         if (pos + RING - 1 < n_tot) issue(pos + RING - 1);
@@ -612,6 +673,7 @@ struct Adjoint {
                 if (!((valid >> k) & 1u) && (64 * (k + 1) <= NE || lane + 64 * k < NE)) slot[64 * k + lane] = 0u;
         }
         wave_lds_sync();
+        wait_vm<0>();
         return reinterpret_cast<const T *>(slot);
     }
 
@@ -625,8 +687,7 @@ struct Adjoint {
 #pragma unroll
             for (int s2 = 0; s2 < S; ++s2) {
                 T g[S];
-#pragma unroll
-                for (int s3 = 0; s3 < S; ++s3) g[s3] = row[s2 * S + s3];
+                lds_row<T, S>(lds_addr(row + s2 * S), g);
                 // the table entries of one s2 at a time in scalar registers (a whole slab's
                 // would not fit beside everything else)
                 cptr<T> t2r[NSET];
@@ -647,8 +708,7 @@ struct Adjoint {
             }
         } else {
             T g[S];
-#pragma unroll
-            for (int s2 = 0; s2 < S; ++s2) g[s2] = row[s2];
+            lds_row<T, S>(lds_addr(row), g);
 #pragma unroll
             for (int m = 0; m < NSET; ++m) {
                 T y = T(0);
@@ -790,9 +850,6 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
     if constexpr (D == 3) fix = fix || t.i2 < P || t.i2 >= sp.n[1] - P;
     A adj{sp, t, ring, lane, ql, gM, gK, s1_lo, n_s1, DO_M ? n_s1 : 0, (DO_M ? n_s1 : 0) + (DO_K ? n_s1 : 0), fix};
     adj.make_map();
-#pragma unroll
-    for (int pos = 0; pos < RING - 1; ++pos)
-        if (pos < adj.n_tot) adj.issue(pos);
     const int64_t rs = (int64_t)Q * S;
     cptr<T> M2 = table<T>(tb, 0, 1) + t.i2 * rs;
     cptr<T> K2 = table<T>(tb, 1, 1) + t.i2 * rs;
@@ -800,12 +857,24 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
     const T *KL = (const T *)tb.t[1][D - 1] + t.il * rs + ql * S;
     cptr<FT> fM1 = final_table<T, FINAL>(tb, 0, 0) + t.i1 * rs;
     cptr<FT> fK1 = final_table<T, FINAL>(tb, 1, 0) + t.i1 * rs;
+    // This lane's last-direction table entries are loaded and consumed before the first
+    // slab is issued, so the compiler's wait for them comes before the stream and not
+    // inside the slab loop (once a direct-to-LDS load is in flight it can only wait for a
+    // register load with a full vmcnt(0); first used under a branch, they would get such a
+    // wait at every slab).  The table rows are a few KB shared by every wave: an L2 hit.
+    // The first RING - 1 slabs always exist: a row reaches at least p + 1 slabs of each
+    // matrix (p + 1 >= 3 >= RING - 1).
     T tlM[S], tlK[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         tlM[s] = ML[s];
         tlK[s] = KL[s];
     }
+    pin(tlM);
+    pin(tlK);
+    static_assert(RING - 1 <= P + 1, "prologue slabs exist in every tile");
+#pragma unroll
+    for (int pos = 0; pos < RING - 1; ++pos) adj.issue(pos);
     if constexpr (DO_M) {
         T tl[1][S];
 #pragma unroll
@@ -1099,8 +1168,8 @@ template <typename T, int P, int D, int WHAT, int FINAL>
 hipError_t run_adjoint(const DevSpace &sp, const DevTabs &tb, const void *gM, const void *gK,
                        void *dc, void *const *da, hipStream_t st) {
     constexpr int Q = P + 1, R = 64 / Q;
-    // ring depth: FP32 4 slabs, FP64 3 slabs; one wave per work-group (measured as fast as
-    // four in FP32 and 10% faster than two in FP64)
+    // ring depth: FP32 4 slabs, FP64 3 slabs (a 2-slab ring measured 1.5% slower in FP32);
+    // one wave per work-group (as fast as four in FP32, 10% faster than two in FP64)
     constexpr int RING = sizeof(T) == 4 ? 4 : 3;
     constexpr int WPB = 1;
     const int tiles = (int)((sp.n[D - 1] + R - 1) / R);
