@@ -152,21 +152,18 @@ __device__ __forceinline__ constexpr bool in_band(int q, int s) {
     return s >= q && s <= q + P;
 }
 
-// Work-group index, optionally remapped so that consecutive indices run on the same
-// XCD: the hardware deals work-groups round-robin over the 8 XCDs (each with its own
-// L2), and neighbouring tiles share the cache lines at their boundaries.
-template <bool XCD>
-__device__ __forceinline__ uint32_t block_index() {
-    const uint32_t b = blockIdx.x;
-    if constexpr (!XCD) return b;
-    const uint32_t nb = gridDim.x, q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+// Work-group index remapped so that each XCD takes one contiguous eighth of the grid: the
+// hardware deals work-groups round-robin over the 8 XCDs (each with its own L2), and
+// neighbouring tiles share the cache lines at their boundaries.
+__device__ __forceinline__ uint32_t block_chunked() {
+    const uint32_t b = blockIdx.x, nb = gridDim.x, q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
 // Work-group index remapped in runs of 8·G: within a run, XCD x takes the G consecutive
 // indices x·G .. x·G+G-1, which it receives G dispatches apart.  Neighbouring tiles then
 // share an L2 while the whole chip still sweeps one contiguous window of tiles (unlike
-// block_index<true>, which gives each XCD its own eighth of the grid).  The incomplete
+// block_chunked(), which gives each XCD its own eighth of the grid).  The incomplete
 // last run keeps the identity, so the map is a permutation of [0, gridDim.x).
 template <int G>
 __device__ __forceinline__ uint32_t block_grouped() {
@@ -926,7 +923,7 @@ __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
     __shared__ __align__(16) uint32_t ring[WPB][RING * A::SLOT];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t task = (int64_t)block_index<true>() * WPB + wave;
+    const int64_t task = (int64_t)block_chunked() * WPB + wave;
     if (task >= n_tasks) return;
     const Tile t = make_tile<D, P, INTERIOR ? kLinesInterior : kLinesBoundary>(sp, task, tiles_per_line, R, Q, lane);
     adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING>(sp, tb, t, ring[wave], lane, gM, gK, dc, da0, da1,
