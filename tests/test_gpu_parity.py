@@ -89,6 +89,30 @@ def test_forward_final_modes_fp32(wqa, case, mode):
     assert st.row_scaled_error(K.cpu().numpy(), Kw) <= 1e-5
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["plain", "compensated", "f64acc"])
+@pytest.mark.parametrize("case", [(3, 3, (5, 4, 13)), (3, 2, (4, 3, 21)), (2, 3, (7, 23))], ids=_ids)
+def test_adjoint_final_modes_fp32(wqa, case, mode):
+    """Every FP32 final pass of the adjoint (running sums, Dot2, FP64 accumulator) against
+    the oracle at every point, both matrices at once."""
+    d, p, n_el = case
+    sp = wqa.Space(d, p, n_el)
+    sp.set_final_mode(mode)
+    n = list(sp.n_basis)
+    rng = np.random.default_rng(57 + 3 * d + p)
+    valid = si.slot_valid_mask(n_el, p).numpy()
+    gM = np.where(valid, rng.normal(size=valid.shape), 0.0)
+    gK = np.where(valid, rng.normal(size=valid.shape), 0.0)
+    dc, da = sp.adjoint(torch.from_numpy(gM).to(sp.device, torch.float32),
+                        torch.from_numpy(gK).to(sp.device, torch.float32))
+    torch.cuda.synchronize()
+    rows = _rows_all(sp)
+    wc, wa = oa.adjoint(p, n_el, oa.rule_tables(p, n_el), gM, gK, rows=rows)
+    pts = st.point_offsets(n, p, rows)
+    assert ph.normwise_error(dc.reshape(-1).cpu().numpy()[pts], wc) <= 1e-5
+    for k in range(d):
+        assert ph.normwise_error(da[k].reshape(-1).cpu().numpy()[pts], wa[k]) <= 1e-5, k
+
+
 @pytest.mark.parametrize("case", SMALL, ids=_ids)
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 @pytest.mark.parametrize("what", ["mass", "stiffness", "both"])
