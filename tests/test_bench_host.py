@@ -1,0 +1,43 @@
+"""Host-side parts of bench.py (no GPU): the one-GPU guard and the lookup of the
+committed HBM counters, which must refuse figures taken on another kernel source."""
+import hashlib
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
+    import bench
+    with open(bench.TRAFFIC_FILE) as f:
+        data = json.load(f)
+    with open(bench.KERNEL_SRC, "rb") as f:
+        current = hashlib.sha256(f.read()).hexdigest() == data["kernel_source_sha256"]
+    kernels = data["kernels"]
+    assert set(kernels) >= {"forward_fp32_mk", "adjoint_fp32_mk"}
+    for name, entry in kernels.items():
+        want = entry["fetch_bytes"] + entry["write_bytes"]
+        # measured bytes sit near the algorithmic ones (within 30%): a summary of some
+        # other workload would not
+        assert 0.7 < want / 16318254696 < 1.3, name
+        # taken on this kernel source: reported; else (kernels changed since): null
+        assert bench.traffic_for(name) == (pytest.approx(want) if current else None)
+    assert bench.traffic_for("no_such_kernel") is None
+    # the same summary against a different kernel source gives no figure at all
+    other = tmp_path / "kernels.hip"
+    other.write_text("// another kernel source\n")
+    monkeypatch.setattr(bench, "KERNEL_SRC", str(other))
+    assert bench.traffic_for("forward_fp32_mk") is None
