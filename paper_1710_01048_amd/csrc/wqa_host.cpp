@@ -491,14 +491,23 @@ struct RowSystem {
 bool trace_row(int p, int kind, int64_t j, int64_t nel, const std::vector<real> &target, const LocalRule &uniform,
                LocalRule &out) {
     RowSystem rs(p, kind, j, nel + p);
+    // The row is solved in coordinates local to its support: every knot is taken relative
+    // to the support's first breakpoint e0, all along the path (differences formed before
+    // they are mixed, so nothing large cancels).  Magnitudes then stay O(p) on every row;
+    // in absolute element units, rows far from the origin sit where one unit in the last
+    // place of a node exceeds Newton's tolerances.  The previous root, carried in these
+    // coordinates, also moves with the support from one step to the next.
+    const int64_t e0 = j - p > 0 ? j - p : 0;
     std::vector<real> br(nel + 1);
     auto knots_at = [&](real lam) {
-        for (int64_t e = 0; e <= nel; ++e) br[e] = (1 - lam) * (real)e + lam * target[e];
+        for (int64_t e = 0; e <= nel; ++e) br[e] = (1 - lam) * (real)(e - e0) + lam * (target[e] - target[e0]);
         return Knots{p, nel, br.data()};
     };
     auto res = [&](const std::vector<real> &v, std::vector<real> &f) { rs.residual(v, f); };
     rs.setup(knots_at(0));
-    std::vector<real> v = rs.unknowns(uniform.tau, uniform.omega);
+    std::vector<real> tau0 = uniform.tau;
+    for (real &x : tau0) x -= (real)e0;
+    std::vector<real> v = rs.unknowns(tau0, uniform.omega);
     real lam = 0, step = (real)0.25;
     while (lam < 1) {
         const real nxt = std::min((real)1, lam + step);
@@ -514,6 +523,7 @@ bool trace_row(int p, int kind, int64_t j, int64_t nel, const std::vector<real> 
         }
     }
     rs.expand(v, out.tau, out.omega);
+    for (real &x : out.tau) x += target[e0];
     return true;
 }
 

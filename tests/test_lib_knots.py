@@ -63,3 +63,24 @@ def test_set_rules_validates_against_the_knots(wqa):
     sp = wqa.Space(2, 3, (N, N), device=None, rules=None, breaks=[MESHES["graded"], None])
     with pytest.raises(wqa.WQAError, match="WQA_ERULE"):
         sp.set_rules(wqa.MASS, 0, x, w)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_large_graded_mesh_every_row_exact(wqa, p):
+    """160 elements graded as (k/N)^1.4: rows far from the origin move by ~10 element
+    widths along the path.  Every traced rule is exact on the target knots, and the row
+    whose trace once failed (130, stiffness) is the oracle's traced rule."""
+    from oracle import nonuniform as nu
+    n_el = 160
+    breaks = [(k / n_el) ** 1.4 for k in range(n_el + 1)]
+    sp = wqa.Space(2, p, (n_el, p + 1), device=None, breaks=[breaks, None])
+    for kind, name in ((wqa.MASS, "mass"), (wqa.STIFFNESS, "stiffness")):
+        x, w = sp.rules(kind, 0)
+        worst = max(nu.exactness_residual(p, breaks, name, j, x[j], w[j]) for j in range(n_el + p))
+        # FP64 nodes in [0, 1] carry ~n_el * 1e-16 element widths of rounding
+        assert worst <= 1e-13, (name, worst)
+    if p == 2:
+        x, w = sp.rules(wqa.STIFFNESS, 0)
+        tau, om = nu.row_rule(p, tuple(float(b) for b in breaks), "stiffness", 130)
+        assert np.abs(x[130] * n_el - np.array([float(t) for t in tau])).max() <= 1e-12
+        assert np.abs(w[130] * n_el - np.array([float(o) for o in om])).max() <= 1e-12
