@@ -133,8 +133,11 @@ wqa_status wqa_set_default_rules(wqa_ctx *ctx);
  * validated: nodes with nonzero weight lie strictly inside supp(B_j) and at least
  * 1e-9 element widths from any knot, and the relative exactness residual over the
  * interacting columns is <= exact_tol (WQA_ERULE otherwise, nothing installed).
- * exact_tol < 0 skips validation.  Copies the arrays; uploads the tables to the
- * device of a device context. */
+ * exact_tol < 0 skips validation.  Nodes in FP64 parametric units carry up to
+ * n_elem * 2^-53 element widths of rounding, so no rule shows a residual much below
+ * that on long directions (wqa_set_default_rules validates its own rules against
+ * max(1e-12, 8 n_elem 2^-53)).  Copies the arrays; uploads the tables to the device of
+ * a device context. */
 wqa_status wqa_set_rules(wqa_ctx *ctx, wqa_kind kind, int dir, int q,
                          const double *nodes, const double *weights, double exact_tol);
 

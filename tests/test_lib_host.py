@@ -131,3 +131,30 @@ def test_misuse_reported(wqa):
     assert rc == -2 and b"host-only" in wqa.lib.wqa_last_error()
     assert wqa.lib.wqa_set_space(None, 2, 2, None) == -1
     assert wqa.lib.wqa_set_final_mode(sp2._ctx, 5) == -1
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_long_uniform_direction(wqa, p):
+    """A direction of 10^6 elements (the ABI allows 2^24): the default rules set up (their
+    validation allows for the rounding of FP64 parametric nodes, up to n_el 2^-53 element
+    widths), every interior rule is the first one translated, the boundary rules are the
+    small space's, and the contraction tables agree up to that rounding."""
+    ne = 10 ** 6
+    sp = wqa.Space(2, p, (ne, p + 1), device=None)
+    small = wqa.Space(2, p, (20, p + 1), device=None)
+    bound = 8 * ne * 2.0 ** -53                       # element widths
+    for kind in (wqa.MASS, wqa.STIFFNESS):
+        x, w = sp.rules(kind, 0)
+        xs, ws = small.rules(kind, 0)
+        n = ne + p
+        interior = np.arange(p, n - p)
+        local = x[interior] * ne - (interior - p)[:, None]
+        assert np.abs(local - local[0]).max() <= bound
+        assert np.all(w[interior] == w[p])
+        for j in range(p):                            # both ends: the small space's rules
+            assert np.abs(x[j] * ne - xs[j] * 20).max() <= bound
+            assert np.abs((1 - x[n - 1 - j]) * ne - (1 - xs[20 + p - 1 - j]) * 20).max() <= bound
+            np.testing.assert_allclose(w[j] * ne, ws[j] * 20, rtol=1e-14)
+        T = sp.tables(kind, 0)
+        far, near = n - 2 * p - 1, 2 * p
+        assert np.abs(T[far] - T[near]).max() <= 64 * bound * np.abs(T[near]).max()
