@@ -572,13 +572,14 @@ bool rules_complete(const wqa_ctx *c) {
 
 // Builds T[j][q][s] = w_jq phi_j(x_jq) phi_{j-p+s}(x_jq) for one kind and direction, in
 // parametric units (the stiffness factor carries nel^2 from d/dx = nel d/du).
-// body(j0, j1) over the rows [0, n) in contiguous chunks on host threads (one chunk
-// below 32768 rows); body must only write state of its own rows.
+// body(j0, j1) over the rows [0, n) in contiguous chunks of at least `grain` rows on
+// host threads (a single call when one chunk remains); body must only write state of
+// its own rows.
 template <class F>
-void for_rows(int64_t n, F body) {
+void for_rows(int64_t n, int64_t grain, F body) {
     const unsigned hw = std::thread::hardware_concurrency();
-    const int64_t chunks = std::min<int64_t>(hw ? hw : 1, (n + 16383) / 16384);
-    if (n < 32768 || chunks <= 1) {
+    const int64_t chunks = std::min<int64_t>(hw ? hw : 1, n / grain);
+    if (chunks <= 1) {
         body((int64_t)0, n);
         return;
     }
@@ -597,7 +598,7 @@ void build_table(wqa_ctx *c, int kind, int dir) {
     std::vector<float> &T32 = c->tab32[kind][dir];
     T32.resize(T.size());
     const std::vector<double> &xs = c->nodes[kind][dir], &ws = c->omega[kind][dir];
-    for_rows(n, [&](int64_t j0, int64_t j1) {
+    for_rows(n, 16384, [&](int64_t j0, int64_t j1) {
         for (int64_t j = j0; j < j1; ++j)
             for (int q = 0; q < Q; ++q) {
                 const real x = xs[j * Q + q];
@@ -762,27 +763,36 @@ wqa_status homotopy_direction(wqa_ctx *c, int kind, const LocalRule &interior, c
     const Knots kn = knots_of(c, dir);
     x.assign((size_t)n * Q, 0.0);
     w.assign((size_t)n * Q, 0.0);
-    for (int64_t j = 0; j < n; ++j) {
-        LocalRule uni, r;
-        if (j >= p && j < n - p) {
-            for (int q = 0; q < Q; ++q) {
-                uni.tau.push_back((real)(j - p) + interior.tau[q]);
-                uni.omega.push_back(interior.omega[q]);
+    // rows are traced independently, on host threads (a trace costs milliseconds)
+    std::vector<LocalRule> traced(n);
+    std::vector<char> found(n, 0);
+    for_rows(n, 4, [&](int64_t j0, int64_t j1) {
+        for (int64_t j = j0; j < j1; ++j) {
+            LocalRule uni;
+            if (j >= p && j < n - p) {
+                for (int q = 0; q < Q; ++q) {
+                    uni.tau.push_back((real)(j - p) + interior.tau[q]);
+                    uni.omega.push_back(interior.omega[q]);
+                }
+            } else if (j < p) {
+                uni = boundary[j];
+            } else {
+                const LocalRule &b = boundary[n - 1 - j];
+                const int m = (int)b.tau.size();
+                for (int q = 0; q < m; ++q) {
+                    uni.tau.push_back(fn - b.tau[m - 1 - q]);
+                    uni.omega.push_back(b.omega[m - 1 - q]);
+                }
             }
-        } else if (j < p) {
-            uni = boundary[j];
-        } else {
-            const LocalRule &b = boundary[n - 1 - j];
-            const int m = (int)b.tau.size();
-            for (int q = 0; q < m; ++q) {
-                uni.tau.push_back(fn - b.tau[m - 1 - q]);
-                uni.omega.push_back(b.omega[m - 1 - q]);
-            }
+            found[j] = trace_row(p, kind, j, nel, c->brk[dir], uni, traced[j]);
         }
-        if (!trace_row(p, kind, j, nel, c->brk[dir], uni, r))
+    });
+    for (int64_t j = 0; j < n; ++j) {
+        if (!found[j])
             return fail(WQA_ERULE, "%s rule of direction %d, row %lld: the homotopy from the uniform rule met a "
                         "singular point (no rule of this family on these knots)",
                         kind == WQA_MASS ? "mass" : "stiffness", dir, (long long)j);
+        const LocalRule &r = traced[j];
         const real pad = j < p ? (kn.brk(0) + kn.brk(1)) / 2 : (kn.brk(nel - 1) + kn.brk(nel)) / 2;
         for (int q = 0; q < Q; ++q) {
             const bool real_node = q < (int)r.tau.size();
