@@ -373,3 +373,40 @@ def test_config5_properties_every_row(wqa, dtype):
     dc, _ = sp.adjoint(gM, None)
     rhs = (dc.double() * c.double()).sum().item()
     assert abs(lhs - rhs) <= tol * scale
+
+
+_LONG_TABLES = {}
+
+
+@pytest.mark.parametrize("case", [(2, 2, (3, 2 ** 16)), (2, 3, (2 ** 16, 4))], ids=_ids)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_long_lines(wqa, case, dtype):
+    """Long directions: 2^16 elements along the last direction (thousands of wave tiles
+    per line) or along the first (65,539 lines).  Fused forward and adjoint on a row
+    sample covering both ends of every direction, against the oracle."""
+    d, p, n_el = case
+    sp = wqa.Space(d, p, n_el)
+    recipe = ("fourier", 2)
+    f = ph.device_fields(sp, recipe, dtype)
+    M, K = sp.assemble_fused(f[0], f[1:])
+    rows = st.sample_rows(list(sp.n_basis), p, 200, seed=16)
+    ridx = torch.from_numpy(rows).to(sp.device)
+    Mg, Kg = M[ridx].double().cpu().numpy(), K[ridx].double().cpu().numpy()
+    del M, K, f
+    rng = np.random.default_rng(17)
+    valid = si.slot_valid_mask(n_el, p).numpy()
+    gM = np.where(valid, rng.normal(size=valid.shape), 0.0)
+    gK = np.where(valid, rng.normal(size=valid.shape), 0.0)
+    dc, da = sp.adjoint(torch.from_numpy(gM).to(sp.device, dtype), torch.from_numpy(gK).to(sp.device, dtype))
+    pts = st.point_offsets(list(sp.n_basis), p, rows)
+    grads = [g.reshape(-1).cpu().numpy()[pts] for g in [dc] + list(da)]
+    if case not in _LONG_TABLES:
+        _LONG_TABLES[case] = oa.rule_tables(p, n_el)
+    tabs = _LONG_TABLES[case]
+    fw = ph.oracle_row_fields(tabs, p, n_el, rows, recipe)
+    Mw, Kw = oa.assemble(p, n_el, tabs, c=fw[0], a=fw[1:], rows=rows, per_row=True)
+    wc, wa = oa.adjoint(p, n_el, tabs, gM[rows], gK[rows], rows=rows)
+    eM, eK = st.row_scaled_error(Mg, Mw), st.row_scaled_error(Kg, Kw)
+    eg = max(ph.normwise_error(g, w) for g, w in zip(grads, [wc] + list(wa)))
+    print(f"long {case} {dtype}: row-scaled M {eM:.3e} K {eK:.3e}; gradients normwise {eg:.3e}")
+    assert eM <= TOL[dtype] and eK <= TOL[dtype] and eg <= TOL[dtype]
