@@ -410,3 +410,34 @@ def test_long_lines(wqa, case, dtype):
     eg = max(ph.normwise_error(g, w) for g, w in zip(grads, [wc] + list(wa)))
     print(f"long {case} {dtype}: row-scaled M {eM:.3e} K {eK:.3e}; gradients normwise {eg:.3e}")
     assert eM <= TOL[dtype] and eK <= TOL[dtype] and eg <= TOL[dtype]
+
+
+def test_beyond_2_31_values_per_matrix(wqa):
+    """210^3 cubic: 9,663,597 rows x 343 = 3.3e9 values per matrix, past 2^31 element
+    offsets.  FP32 fused forward, then the adjoint with the assembled M and K as upstream
+    gradients, on a row sample that includes the last rows, against the oracle."""
+    p, n_el = 3, (210, 210, 210)
+    sp = wqa.Space(3, p, n_el)
+    assert sp.n_rows * sp.slots_per_row > 2 ** 31
+    recipe = ("fourier", 5)
+    f = ph.device_fields(sp, recipe, torch.float32)
+    M, K = sp.assemble_fused(f[0], f[1:])
+    del f
+    last = sp.n_rows - 1
+    rows = np.unique(np.concatenate([st.sample_rows(list(sp.n_basis), p, 200, seed=210),
+                                     [last - 213 * 213, last - 213, last - 9, last - 1, last]]))
+    ridx = torch.from_numpy(rows).to(sp.device)
+    Mg, Kg = M[ridx].double().cpu().numpy(), K[ridx].double().cpu().numpy()
+    dc, da = sp.adjoint(M, K)
+    pts = torch.from_numpy(st.point_offsets(list(sp.n_basis), p, rows).reshape(-1)).to(sp.device)
+    grads = [g.reshape(-1)[pts].double().cpu().numpy().reshape(rows.size, -1) for g in [dc] + list(da)]
+    del M, K, dc, da
+    torch.cuda.empty_cache()
+    tabs = oa.rule_tables(p, n_el)
+    fw = ph.oracle_row_fields(tabs, p, n_el, rows, recipe)
+    Mw, Kw = oa.assemble(p, n_el, tabs, c=fw[0], a=fw[1:], rows=rows, per_row=True)
+    wc, wa = oa.adjoint(p, n_el, tabs, Mg, Kg, rows=rows)
+    eM, eK = st.row_scaled_error(Mg, Mw), st.row_scaled_error(Kg, Kw)
+    eg = max(ph.normwise_error(g, w) for g, w in zip(grads, [wc] + list(wa)))
+    print(f"210^3 f32: row-scaled M {eM:.3e} K {eK:.3e}; gradients normwise {eg:.3e}")
+    assert eM <= 1e-5 and eK <= 1e-5 and eg <= 1e-5
