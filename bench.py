@@ -373,11 +373,19 @@ def main():
     # (read by the forward, written by the adjoint), 4 bytes each in FP32
     alg_bytes = sp.n_rows * (2 * sp.slots_per_row + 4 * sp.points_per_row) * 4
 
+    # the writes alone: the forward writes the two matrices, the adjoint the four gradients
+    write_bytes = {"forward_fp32_mk": sp.n_rows * 2 * sp.slots_per_row * 4,
+                   "adjoint_fp32_mk": sp.n_rows * 4 * sp.points_per_row * 4}
+    best_probe = max(probe.values())
+
     def roof(ms, kernel):
         achieved = alg_bytes / (ms * 1e-3) / 1e9
         traffic = traffic_for(kernel)
+        wb = write_bytes[kernel]
         return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": alg_bytes}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": alg_bytes,
+                "write_bytes": wb, "write_frac": wb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "frac_of_best_probe": achieved / best_probe}
 
     roof_fwd = roof(r32["fwd_ms"], "forward_fp32_mk")
     roof_adj = roof(r32["adj_ms"], "adjoint_fp32_mk")
