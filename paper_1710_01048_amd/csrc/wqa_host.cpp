@@ -572,13 +572,23 @@ bool rules_complete(const wqa_ctx *c) {
 
 // Builds T[j][q][s] = w_jq phi_j(x_jq) phi_{j-p+s}(x_jq) for one kind and direction, in
 // parametric units (the stiffness factor carries nel^2 from d/dx = nel d/du).
+// Host threads for setup work: OMP_NUM_THREADS when set (the process's share of the
+// host), else the hardware's count; at most 64.
+int64_t host_threads() {
+    int64_t t = (int64_t)std::thread::hardware_concurrency();
+    if (const char *env = std::getenv("OMP_NUM_THREADS")) {
+        const long v = std::strtol(env, nullptr, 10);
+        if (v > 0) t = v;
+    }
+    return std::max<int64_t>(1, std::min<int64_t>(t, 64));
+}
+
 // body(j0, j1) over the rows [0, n) in contiguous chunks of at least `grain` rows on
 // host threads (a single call when one chunk remains); body must only write state of
 // its own rows.
 template <class F>
 void for_rows(int64_t n, int64_t grain, F body) {
-    const unsigned hw = std::thread::hardware_concurrency();
-    const int64_t chunks = std::min<int64_t>(hw ? hw : 1, n / grain);
+    const int64_t chunks = std::min<int64_t>(host_threads(), n / grain);
     if (chunks <= 1) {
         body((int64_t)0, n);
         return;
