@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--skip-modes", action="store_true", help="time only the headline final pass")
     ap.add_argument("--headline-only", action="store_true",
                     help="leave out the other workloads (matrix-free products, 96^3 forward): profiler runs")
+    ap.add_argument("--cube96-only", action="store_true",
+                    help="run only the 96^3 deformed-cube forward and print its figures (profiler runs)")
     ap.add_argument("--profile-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -297,6 +299,9 @@ def main():
     from paper_1710_01048_amd import counts
     assert torch.cuda.is_available(), "needs a HIP device"
     dev = torch.device("cuda:0")
+    if args.cube96_only:
+        print(json.dumps({"forward_96cubed_deformed_cube": deformed_cube_forward(wqa, dev)}), flush=True)
+        return
     if args.profile_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
         dst = torch.empty_like(src)
