@@ -8,11 +8,11 @@ arithmetic.  Coefficients are evaluated at whatever coordinates the caller passe
 Recipes (the paper uses no public data set; its numerical examples are all
 synthetic problems on the unit square / cube):
 
-* ``config1_c``: c(x, y) = 1 + 0.5 sin(2 pi x) sin(2 pi y).
+* ``sin_product_c``: c(x, y) = 1 + 0.5 sin(2 pi x) sin(2 pi y).
 * ``fourier_modes`` / ``fourier_grid`` / ``fourier_points``: f(x) = 1 + sum_{m<8}
   alpha_m cos(2 pi k_m . x + phi_m), k_m uniform in {0..3}^d without the zero vector,
   phi_m ~ U(0, 2 pi), alpha_m ~ U(0, 0.3), drawn (k, then phi, then alpha) from
-  numpy.random.default_rng(1000 * config + field); field 0 is c, fields 1..d are a_k.
+  numpy.random.default_rng(1000 * family + field); field 0 is c, fields 1..d are a_k.
 * ``deformed_cube``: the map G_k(x) = x_k + 0.05 sin(2 pi x_k) of the unit cube onto
   itself, whose Jacobian J = diag(1 + 0.1 pi cos(2 pi x_k)) is folded into the
   coefficients of the pulled-back forms (eq:Mass and eq:Stiffness with physical c = 1,
@@ -28,15 +28,15 @@ import torch
 N_MODES = 8
 
 
-def config1_c(x, y):
+def sin_product_c(x, y):
     """c(x, y) = 1 + 0.5 sin(2 pi x) sin(2 pi y) (any broadcastable torch/numpy arrays)."""
     lib = torch if isinstance(x, torch.Tensor) else np
     return 1.0 + 0.5 * lib.sin(2 * math.pi * x) * lib.sin(2 * math.pi * y)
 
 
-def fourier_modes(config, field, d):
+def fourier_modes(family, field, d):
     """(k [8, d] int64, phi [8], alpha [8]) of one random Fourier field."""
-    rng = np.random.default_rng(1000 * config + field)
+    rng = np.random.default_rng(1000 * family + field)
     ks = []
     while len(ks) < N_MODES:
         k = rng.integers(0, 4, size=d)

@@ -5,8 +5,8 @@ the oracle), plus the error metrics of the comparisons.
 recipe:
   ("random", seed)      i.i.d. U(0.5, 1.5) samples on the grid -- one host array, the
                         same values go to both sides (node positions do not matter)
-  ("config1",)          c = 1 + 0.5 sin(2 pi x) sin(2 pi y), a_k = 1
-  ("fourier", config)   random Fourier fields of that config (field 0 = c, k+1 = a_k)
+  ("sin_product",)      c = 1 + 0.5 sin(2 pi x) sin(2 pi y), a_k = 1
+  ("fourier", family)   random Fourier fields of that seed family (field 0 = c, k+1 = a_k)
   ("deformed",)         deformed-cube coefficients (det J, det J / J_kk^2)
 """
 import numpy as np
@@ -37,11 +37,11 @@ def device_fields(space, recipe, dtype):
     out = []
     for field in ["c"] + list(range(d)):
         axes = space.grid_axes(field)
-        if kind == "config1":
+        if kind == "sin_product":
             if field == "c":
                 x = torch.tensor(axes[0], dtype=torch.float64, device=dev)[:, None]
                 y = torch.tensor(axes[1], dtype=torch.float64, device=dev)[None, :]
-                out.append(si.config1_c(x, y).to(dtype).contiguous())
+                out.append(si.sin_product_c(x, y).to(dtype).contiguous())
             else:
                 out.append(torch.ones(space.grid_shape, dtype=dtype, device=dev))
         elif kind == "fourier":
@@ -67,8 +67,8 @@ def oracle_row_fields(tabs, p, n_el, rows, recipe):
     for field in ["c"] + list(range(d)):
         xyz = oa.row_point_coords(p, n_el, tabs, rows, field)          # [n_list, QD, d]
         flat = xyz.reshape(-1, d)
-        if kind == "config1":
-            v = si.config1_c(flat[:, 0], flat[:, 1]) if field == "c" else np.ones(len(flat))
+        if kind == "sin_product":
+            v = si.sin_product_c(flat[:, 0], flat[:, 1]) if field == "c" else np.ones(len(flat))
         elif kind == "fourier":
             fid = 0 if field == "c" else field + 1
             v = si.fourier_points(flat, si.fourier_modes(recipe[1], fid, d))

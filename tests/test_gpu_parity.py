@@ -143,10 +143,10 @@ def test_adjoint_small_every_point(wqa, case, dtype, what):
             assert ph.normwise_error(got, wa[k]) <= TOL[dtype], k
 
 
-def test_config1_mass_2d_quadratic(wqa):
+def test_mass_2d_quadratic_32x32(wqa):
     # 2D C^1 quadratic, 32 x 32 elements, c = 1 + 0.5 sin sin, FP64 mass (every row)
     sp = wqa.Space(2, 2, (32, 32))
-    recipe = ("config1",)
+    recipe = ("sin_product",)
     f = ph.device_fields(sp, recipe, torch.float64)
     M = sp.assemble_mass(f[0])
     Mw, _ = ph.oracle_forward(2, (32, 32), _rows_all(sp), recipe, want_k=False)
@@ -171,23 +171,23 @@ def _sampled_forward(wqa, d, p, n_el, recipe, dtype, mode=None, count=300):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_config2_fused_3d_quadratic(wqa, dtype):
+def test_fused_3d_quadratic_64_cubed(wqa, dtype):
     eM, eK, eMe = _sampled_forward(wqa, 3, 2, (64, 64, 64), ("fourier", 2), dtype)
-    print(f"config2 {dtype}: row-scaled M {eM:.3e} K {eK:.3e}; entrywise M {eMe:.3e}")
+    print(f"64^3 quadratic {dtype}: row-scaled M {eM:.3e} K {eK:.3e}; entrywise M {eMe:.3e}")
     assert eM <= TOL[dtype] and eK <= TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype,mode", [(torch.float64, None), (torch.float32, 1),
                                         (torch.float32, 0), (torch.float32, 2)],
                          ids=["f64", "f32-dot2", "f32-plain", "f32-f64acc"])
-def test_config3_fused_3d_cubic_deformed(wqa, dtype, mode):
+def test_fused_3d_cubic_deformed_96_cubed(wqa, dtype, mode):
     eM, eK, eMe = _sampled_forward(wqa, 3, 3, (96, 96, 96), ("deformed",), dtype, mode)
-    print(f"config3 {dtype} mode {mode}: row-scaled M {eM:.3e} K {eK:.3e}; entrywise M {eMe:.3e}")
+    print(f"96^3 deformed cube {dtype} mode {mode}: row-scaled M {eM:.3e} K {eK:.3e}; entrywise M {eMe:.3e}")
     assert eM <= TOL[dtype] and eK <= TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_config4_adjoint_3d_cubic(wqa, dtype):
+def test_adjoint_3d_cubic_64_cubed(wqa, dtype):
     # 64^3 cubic, Fourier coefficients, G ~ N(0,1) (seeds 4001, 4002), gradients through
     # the autograd Function, sampled rows against the oracle's adjoint
     p, n_el = 3, (64, 64, 64)
@@ -205,12 +205,12 @@ def test_config4_adjoint_3d_cubic(wqa, dtype):
                         rows=rows)
     errs = [ph.normwise_error(f[0].grad.reshape(-1).cpu().numpy()[pts], wc)]
     errs += [ph.normwise_error(f[k + 1].grad.reshape(-1).cpu().numpy()[pts], wa[k]) for k in range(3)]
-    print(f"config4 {dtype}: normwise gradient errors {['%.3e' % e for e in errs]}")
+    print(f"64^3 adjoint {dtype}: normwise gradient errors {['%.3e' % e for e in errs]}")
     assert max(errs) <= TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_config5_forward_adjoint_160_cubed(wqa, dtype):
+def test_forward_adjoint_160_cubed(wqa, dtype):
     # the benchmark workload at full size, in the launch configuration the benchmark
     # times (default rules and final pass): 160^3 cubic, Fourier c and a_k, fused forward
     # then adjoint with G ~ N(0,1) (seeds 5001, 5002); a row sample covering every
@@ -236,11 +236,11 @@ def test_config5_forward_adjoint_160_cubed(wqa, dtype):
     wc, wa = oa.adjoint(p, n_el, oa.rule_tables(p, n_el), gm, gk, rows=rows)
     eM, eK = st.row_scaled_error(Mg, Mw), st.row_scaled_error(Kg, Kw)
     eg = max(ph.normwise_error(g, w) for g, w in zip(grads, [wc] + list(wa)))
-    print(f"config5 {dtype}: row-scaled M {eM:.3e} K {eK:.3e}; gradients normwise {eg:.3e}")
+    print(f"160^3 {dtype}: row-scaled M {eM:.3e} K {eK:.3e}; gradients normwise {eg:.3e}")
     assert eM <= TOL[dtype] and eK <= TOL[dtype] and eg <= TOL[dtype]
 
 
-def test_config4_central_differences(wqa):
+def test_central_differences_64_cubed(wqa):
     # dL/dtheta at 64 seeded quadrature points (16 per field) against central
     # differences h = 1e-6 in FP64 of L = <G_M, M> + <G_K, K>, evaluated by the oracle
     # on the one row that owns the point; points whose rule weight is 0 are skipped
@@ -321,7 +321,7 @@ def test_errors_surface(wqa):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_config5_properties_every_row(wqa, dtype):
+def test_properties_every_row_160_cubed(wqa, dtype):
     # 160^3 cubic in the benchmark's launch configuration, properties that hold at any
     # size, checked on all 4.33 M rows: with c = 1 the rows of M sum to the integral of
     # B_i (a product of (t_{i+p+1} - t_i)/(p+1) over directions) and M is symmetric; the

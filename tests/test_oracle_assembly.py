@@ -151,7 +151,7 @@ def test_variable_coefficient_converges_at_first_order(p):
         n_el = (ne, ne)
         tabs = oa.rule_tables(p, n_el)
         axes = oa.grid_axes(tabs, "c")
-        c = si.config1_c(axes[0][:, None], axes[1][None, :])
+        c = si.sin_product_c(axes[0][:, None], axes[1][None, :])
         M, _ = oa.assemble(p, n_el, tabs, c=c)
         # exact: c(x, y) = 1 + 0.5 sin sin is a sum of separable terms
         M1 = r1.gram(p, ne, m=12)
