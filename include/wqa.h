@@ -96,8 +96,8 @@ wqa_status wqa_create(wqa_ctx **out, int hip_device);
 void wqa_destroy(wqa_ctx *ctx);
 
 /* Sets the spline space: dimension dim in {2, 3}, degree in {2, 3}, n_elem[dim]
- * elements per direction (each >= degree + 1), open uniform knots on [0, 1]
- * (eq:Gmap3).  Discards any rules set before. */
+ * elements per direction (each in [degree + 1, 2^24]; WQA_EINVAL otherwise), open
+ * uniform knots on [0, 1] (eq:Gmap3).  Discards any rules set before. */
 wqa_status wqa_set_space(wqa_ctx *ctx, int dim, int degree, const int64_t *n_elem);
 
 /* Sets the knots of direction dir to the open knot vector with breakpoints
