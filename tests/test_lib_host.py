@@ -131,6 +131,12 @@ def test_misuse_reported(wqa):
     assert rc == -2 and b"host-only" in wqa.lib.wqa_last_error()
     assert wqa.lib.wqa_set_space(None, 2, 2, None) == -1
     assert wqa.lib.wqa_set_final_mode(sp2._ctx, 5) == -1
+    # element counts: degree + 1 .. 2^24 per direction (no rules are built here)
+    ne = (ctypes.c_int64 * 2)
+    assert wqa.lib.wqa_set_space(sp2._ctx, 2, 3, ne(4, 2 ** 24)) == 0
+    assert wqa.lib.wqa_set_space(sp2._ctx, 2, 3, ne(4, 2 ** 24 + 1)) == -1
+    assert wqa.lib.wqa_set_space(sp2._ctx, 2, 3, ne(3, 8)) == -1
+    assert wqa.lib.wqa_set_space(sp2._ctx, 2, 3, ne(-4, 8)) == -1
 
 
 @pytest.mark.parametrize("p", [2, 3])
