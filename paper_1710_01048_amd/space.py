@@ -18,8 +18,9 @@ def _stream_handle(device):
 
 
 class Space:
-    """Open uniform tensor-product B-spline space of degree 2 or 3 in 2 or 3 dimensions
-    (Sec. 2.2) with its weighted Gaussian row rules (Sec. 3).
+    """Open tensor-product B-spline space of degree 2 or 3 in 2 or 3 dimensions, uniform
+    knots unless ``breaks`` says otherwise (Sec. 2.2), with its weighted Gaussian row
+    rules (Sec. 3).  Each direction takes degree + 1 to 2^24 elements.
 
     device: a torch CUDA (HIP) device, or None for a host-only space (rules and tables
     only; the assemble calls then fail).  rules: "default" installs the library's
