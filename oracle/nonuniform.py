@@ -30,6 +30,11 @@ node's weight diverges.  The row then has no rule of this family and the solver 
 Boundary rows keep their square systems (the exactness conditions completed by the
 truncated powers (x - t)_+^(deg+1) at the first distinct knots from the clamped end,
 ``rules.BOUNDARY_PRESCRIPTION``), now with the actual knots.
+
+Parity unpinned: the paper prints no rule on non-uniform knots.  These rules are pinned
+by their exactness on the target knots, by reducing to the paper's rules on uniform
+breakpoints, and by the conditions above holding; the particular member of each family
+is this reading's choice.
 """
 import functools
 

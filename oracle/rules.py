@@ -25,6 +25,9 @@ What is computed here, and where the paper states it:
   deg = p for mass and p-1 for stiffness), with the node counts listed in
   ``BOUNDARY_PRESCRIPTION``.  Every such system has exactly one admissible root
   (nodes strictly inside the support, off knots, increasing; all omega > 0).
+  Parity unpinned: the paper gives no boundary-row values, so the node positions
+  of these rows are pinned only through their exactness (and the library's own
+  solver agreeing with this one), not against printed numbers.
 
 All solving is done with mpmath at 40 significant digits; tables handed to the
 FP64 assembly are rounded once at the end.
