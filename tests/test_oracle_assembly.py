@@ -233,3 +233,52 @@ def test_adjoint_matches_central_differences():
         fd = ((gM[r] * (Mp - Mm)).sum() + (gK[r] * (Kp - Km)).sum()) / (2 * h)
         got = gc[r, q] if field == 0 else ga[field - 1][r, q]
         assert abs(fd - got) <= 1e-7 * max(1.0, abs(got)), (trial, fd, got)
+
+
+@pytest.mark.parametrize("p,n_el", [(2, (3, 4)), (3, (4, 5)), (2, (3, 4, 3)), (3, (4, 4, 5))])
+def test_single_point_coefficient_touches_only_its_row(p, n_el):
+    """A coefficient nonzero at one sample point (node q of row i) gives nonzeros in row i
+    only, equal to prod_k w_k B_{i_k}(x_k) B_{i_k - p + s_k}(x_k): the weight multiplies
+    both functions (eq:GaussQuadSys) and slot s_k is column i_k - p + s_k (Fig. 1).  For
+    term k of K the stiffness node, weight and B' stand in direction k and the mass ones
+    elsewhere (eq:Decompo).  Basis values from scipy, not the oracle's recursion; a
+    transposed product, a shifted slot or a swapped direction fails here."""
+    d = len(n_el)
+    n = [e + p for e in n_el]
+    Q, S = p + 1, 2 * p + 1
+    tabs = oa.rule_tables(p, n_el)
+    shape = _grid_shape(p, n_el)
+    rng = np.random.default_rng(11 + p + d)
+
+    def factor(k, i, q, deriv, xs, ws):
+        x, w = xs[k][i[k] * Q + q[k]], ws[k][i[k] * Q + q[k]]
+        B = r1.basis_at(p, n_el[k], [x], deriv=deriv)[0]
+        out = np.zeros(S)
+        for s in range(S):
+            col = i[k] - p + s
+            if 0 <= col < n[k]:
+                out[s] = w * B[i[k]] * B[col]
+        return out
+
+    for _ in range(4):
+        i = [int(rng.integers(0, nk)) for nk in n]
+        q = [int(rng.integers(0, Q)) for _ in range(d)]
+        kk = int(rng.integers(0, d))
+        point = tuple(i[k] * Q + q[k] for k in range(d))
+        c = np.zeros(shape)
+        c[point] = 1.0
+        a = [np.zeros(shape) for _ in range(d)]
+        a[kk][point] = 1.0
+        M, K = oa.assemble(p, n_el, tabs, c=c, a=a)
+        expM = factor(0, i, q, False, tabs["xM"], tabs["wM"])
+        expK = factor(0, i, q, kk == 0, tabs["xK"] if kk == 0 else tabs["xM"], tabs["wK"] if kk == 0 else tabs["wM"])
+        for k in range(1, d):
+            expM = np.kron(expM, factor(k, i, q, False, tabs["xM"], tabs["wM"]))
+            stiff = k == kk
+            expK = np.kron(expK, factor(k, i, q, stiff, tabs["xK"] if stiff else tabs["xM"],
+                                        tabs["wK"] if stiff else tabs["wM"]))
+        row = int(np.ravel_multi_index(i, n))
+        others = np.arange(M.shape[0]) != row
+        assert not M[others].any() and not K[others].any()
+        np.testing.assert_allclose(M[row], expM, rtol=0, atol=1e-14 * max(np.abs(expM).max(), 1e-300))
+        np.testing.assert_allclose(K[row], expK, rtol=0, atol=1e-13 * max(np.abs(expK).max(), 1e-300))
