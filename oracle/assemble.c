@@ -271,14 +271,16 @@ int oracle_assemble_rows(int d, int p, const int64_t *n_el, const double *const 
  *   da[k][r][q] = dL/da_k at the q-th point of that row on a_k's grid.
  * gM, gK are [n_list][S^d] rows of the upstream gradient; slots whose column falls
  * outside the space are ignored.  Either side may be NULL (its outputs are then not
- * written).  Returns 0, -1 for bad arguments, -2 when out of memory.
+ * written).  absolute != 0 sums the magnitudes of the same terms instead,
+ * sum_s |G[s]| prod_k |factor_k|: the scale against which a rounding error of one
+ * gradient entry is measured.  Returns 0, -1 for bad arguments, -2 when out of memory.
  */
-int oracle_adjoint(int d, int p, const int64_t *n_el, const double *const *brk,
-                   const double *const *xM, const double *const *wM,
-                   const double *const *xK, const double *const *wK,
-                   const int64_t *rows, int64_t n_list,
-                   const double *gM, const double *gK,
-                   double *dc, double *const *da)
+static int adjoint_impl(int d, int p, const int64_t *n_el, const double *const *brk,
+                        const double *const *xM, const double *const *wM,
+                        const double *const *xK, const double *const *wK,
+                        const int64_t *rows, int64_t n_list,
+                        const double *gM, const double *gK,
+                        double *dc, double *const *da, int absolute)
 {
     space_t sp;
     int rc = space_init(&sp, d, p, n_el, brk);
@@ -309,8 +311,8 @@ int oracle_adjoint(int d, int p, const int64_t *n_el, const double *const *brk,
                     int s[MAXD];
                     decode(sc, sp.S, d, s);
                     if (!slot_valid(&sp, idx, s)) continue;
-                    double prod = gM[r * SD + sc];
-                    for (int k = 0; k < d; ++k) prod *= fM[k][q[k]][s[k]];
+                    double prod = absolute ? fabs(gM[r * SD + sc]) : gM[r * SD + sc];
+                    for (int k = 0; k < d; ++k) prod *= absolute ? fabs(fM[k][q[k]][s[k]]) : fM[k][q[k]][s[k]];
                     acc += prod;
                 }
                 dc[r * QD + qc] = acc;
@@ -322,9 +324,11 @@ int oracle_adjoint(int d, int p, const int64_t *n_el, const double *const *brk,
                         int s[MAXD];
                         decode(sc, sp.S, d, s);
                         if (!slot_valid(&sp, idx, s)) continue;
-                        double prod = gK[r * SD + sc];
-                        for (int k = 0; k < d; ++k)
-                            prod *= (k == kk) ? fK[k][q[k]][s[k]] : fM[k][q[k]][s[k]];
+                        double prod = absolute ? fabs(gK[r * SD + sc]) : gK[r * SD + sc];
+                        for (int k = 0; k < d; ++k) {
+                            const double f = (k == kk) ? fK[k][q[k]][s[k]] : fM[k][q[k]][s[k]];
+                            prod *= absolute ? fabs(f) : f;
+                        }
                         acc += prod;
                     }
                     da[kk][r * QD + qc] = acc;
@@ -334,4 +338,25 @@ int oracle_adjoint(int d, int p, const int64_t *n_el, const double *const *brk,
     }
     space_free(&sp);
     return bad ? -1 : 0;
+}
+
+int oracle_adjoint(int d, int p, const int64_t *n_el, const double *const *brk,
+                   const double *const *xM, const double *const *wM,
+                   const double *const *xK, const double *const *wK,
+                   const int64_t *rows, int64_t n_list,
+                   const double *gM, const double *gK,
+                   double *dc, double *const *da)
+{
+    return adjoint_impl(d, p, n_el, brk, xM, wM, xK, wK, rows, n_list, gM, gK, dc, da, 0);
+}
+
+/* Same arguments as oracle_adjoint; writes sum_s |G[s]| prod_k |factor_k| per point. */
+int oracle_adjoint_abs(int d, int p, const int64_t *n_el, const double *const *brk,
+                       const double *const *xM, const double *const *wM,
+                       const double *const *xK, const double *const *wK,
+                       const int64_t *rows, int64_t n_list,
+                       const double *gM, const double *gK,
+                       double *dc, double *const *da)
+{
+    return adjoint_impl(d, p, n_el, brk, xM, wM, xK, wK, rows, n_list, gM, gK, dc, da, 1);
 }

@@ -55,6 +55,8 @@ def _lib():
                                    P(ctypes.c_double), P(ctypes.c_double),
                                    P(ctypes.c_double), dpp]
     lib.oracle_adjoint.restype = ctypes.c_int
+    lib.oracle_adjoint_abs.argtypes = lib.oracle_adjoint.argtypes
+    lib.oracle_adjoint_abs.restype = ctypes.c_int
     return lib
 
 
@@ -169,10 +171,14 @@ def assemble(p, n_el, tables, c=None, a=None, rows=None, per_row=False):
     return M, K
 
 
-def adjoint(p, n_el, tables, gM=None, gK=None, rows=None):
+def adjoint(p, n_el, tables, gM=None, gK=None, rows=None, absolute=False):
     """Gradients of <gM, M> + <gK, K> with respect to the coefficient samples of the
     listed rows: dc [n_list, (p+1)^d] and da = list of d such arrays (None where the
-    matching upstream gradient is None).  gM, gK are [n_list, (2p+1)^d]."""
+    matching upstream gradient is None).  gM, gK are [n_list, (2p+1)^d].
+
+    absolute=True returns, in the same layout, the sum of the magnitudes of the terms
+    each gradient entry sums, sum_s |G[s]| prod_k |factor_k(q, s)|: the scale of the
+    rounding error any evaluation order of that sum can make."""
     d = len(n_el)
     lib = _lib()
     ne = np.ascontiguousarray(np.array(n_el, dtype=np.int64))
@@ -189,7 +195,8 @@ def adjoint(p, n_el, tables, gM=None, gK=None, rows=None):
     xK, wK = _ptr_array(tables["xK"]), _ptr_array(tables["wK"])
     keep = [xM, wM, xK, wK]
     brk = _breaks_ptr(tables, keep)
-    rc = lib.oracle_adjoint(
+    fn = lib.oracle_adjoint_abs if absolute else lib.oracle_adjoint
+    rc = fn(
         d, p, ne.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), brk, xM, wM, xK, wK,
         None if rows_arr is None else rows_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
         n_list,

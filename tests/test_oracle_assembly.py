@@ -282,3 +282,133 @@ def test_single_point_coefficient_touches_only_its_row(p, n_el):
         assert not M[others].any() and not K[others].any()
         np.testing.assert_allclose(M[row], expM, rtol=0, atol=1e-14 * max(np.abs(expM).max(), 1e-300))
         np.testing.assert_allclose(K[row], expK, rtol=0, atol=1e-13 * max(np.abs(expK).max(), 1e-300))
+
+
+def _graded(n):
+    return tuple((k / n) ** 1.4 for k in range(n + 1))
+
+
+def _perturbed(n, seed=3, amp=0.15):
+    rng = np.random.default_rng(seed)
+    b = np.arange(n + 1) / n + np.concatenate([[0], rng.uniform(-amp, amp, n - 1), [0]]) / n
+    return tuple(float(x) for x in b)
+
+
+def _smooth_field(xyz, field):
+    """A smooth test field at points [..., d], different for every field index."""
+    d = xyz.shape[-1]
+    out = 1.0 + 0.2 * np.prod(xyz, axis=-1)
+    for k in range(d):
+        out = out + 0.3 * np.cos(2 * np.pi * (k + 1 + field) * xyz[..., k] + 0.7 * k + field)
+    return out
+
+
+@pytest.mark.parametrize("p,n_el,meshes", [
+    (2, (4, 5), (None, None)), (3, (5, 6), (None, "graded")),
+    (2, (3, 4, 5), (None, None, None)), (2, (6, 3, 6), ("perturbed", None, "graded")),
+    (3, (4, 5, 4), (None, None, None)),
+])
+def test_per_row_samples_equal_full_grid(p, n_el, meshes):
+    """The oracle's per-row input mode (samples of the listed rows only, gathered with
+    row_points from a grid, or evaluated at row_point_coords) gives the rows the
+    full-grid mode gives: every point of a row is the grid point (i_k (p+1) + q_k)_k of
+    that field's own grid (the mass nodes, or the stiffness nodes in direction k), in C
+    order over q.  A wrong q order, a transposed gather or a field's grid taken for
+    another's fails here."""
+    d = len(n_el)
+    breaks = None
+    if any(m is not None for m in meshes):
+        breaks = [None if m is None else (_graded(e) if m == "graded" else _perturbed(e))
+                  for m, e in zip(meshes, n_el)]
+    tabs = oa.rule_tables(p, n_el, breaks)
+    n = [e + p for e in n_el]
+    rng = np.random.default_rng(23 + p + d)
+    rows = np.unique(np.concatenate([[0, int(np.prod(n)) - 1],
+                                     rng.integers(0, int(np.prod(n)), size=25)]))
+    # random samples: one grid per field, gathered with row_points
+    shape = _grid_shape(p, n_el)
+    grids = [rng.normal(size=shape) for _ in range(d + 1)]
+    pts = oa.row_points(p, n_el, rows)
+    assert np.array_equal(pts, st.point_offsets(n, p, rows))
+    Mf, Kf = oa.assemble(p, n_el, tabs, c=grids[0], a=grids[1:], rows=rows)
+    Mr, Kr = oa.assemble(p, n_el, tabs, c=grids[0].reshape(-1)[pts],
+                         a=[g.reshape(-1)[pts] for g in grids[1:]], rows=rows, per_row=True)
+    assert np.array_equal(Mf, Mr) and np.array_equal(Kf, Kr)
+    # a smooth field of the coordinates: on the full grid of each field's own axes, and at
+    # the coordinates row_point_coords gives for the listed rows
+    full, per_row = [], []
+    for fi, field in enumerate(["c"] + list(range(d))):
+        axes = oa.grid_axes(tabs, field)
+        mesh = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1)
+        full.append(_smooth_field(mesh, fi))
+        per_row.append(_smooth_field(oa.row_point_coords(p, n_el, tabs, rows, field), fi))
+    Mf, Kf = oa.assemble(p, n_el, tabs, c=full[0], a=full[1:], rows=rows)
+    Mr, Kr = oa.assemble(p, n_el, tabs, c=per_row[0], a=per_row[1:], rows=rows, per_row=True)
+    np.testing.assert_allclose(Mr, Mf, rtol=0, atol=1e-14 * np.abs(Mf).max())
+    np.testing.assert_allclose(Kr, Kf, rtol=0, atol=1e-14 * np.abs(Kf).max())
+    # the fields differ from each other, so a swapped field would not pass the above
+    assert np.abs(per_row[1] - per_row[2]).max() > 0.1
+
+
+@pytest.mark.parametrize("p,n_el", [(2, (3, 4)), (3, (4, 5)), (2, (3, 4, 3)), (3, (4, 4, 5))])
+def test_adjoint_and_term_magnitudes_from_scipy_factors(p, n_el):
+    """Every gradient entry is sum_s G[s] prod_k f_k(q_k, s_k), with
+    f_k = w B_{i_k}(x) B_{i_k - p + s_k}(x) at node q_k of row i_k (B' and the stiffness
+    rule in direction k' for da_k', eq:Decompo), and the oracle's absolute variant is
+    sum_s |G[s]| prod_k |f_k|.  Factors from scipy's B-splines, sums by einsum over
+    every row; slots outside the space hold NaN for the oracle and must be skipped."""
+    d = len(n_el)
+    n = [e + p for e in n_el]
+    Q, S = p + 1, 2 * p + 1
+    tabs = oa.rule_tables(p, n_el)
+
+    def factors(k, kind):
+        xs, ws = (tabs["xM"][k], tabs["wM"][k]) if kind == "mass" else (tabs["xK"][k], tabs["wK"][k])
+        B = r1.basis_at(p, n_el[k], xs, deriv=(kind == "stiffness"))          # [n Q, n]
+        F = np.zeros((n[k], Q, S))
+        for i in range(n[k]):
+            for q in range(Q):
+                for s in range(S):
+                    col = i - p + s
+                    if 0 <= col < n[k]:
+                        F[i, q, s] = ws[i * Q + q] * B[i * Q + q, i] * B[i * Q + q, col]
+        return F
+
+    FM = [factors(k, "mass") for k in range(d)]
+    FK = [factors(k, "stiffness") for k in range(d)]
+    rows = np.arange(int(np.prod(n)))
+    idx = st.row_multi(n, rows)
+    valid = si.slot_valid_mask(n_el, p).numpy()
+    rng = np.random.default_rng(41 + p + d)
+    gM = np.where(valid, rng.normal(size=valid.shape), 0.0)
+    gK = np.where(valid, rng.normal(size=valid.shape), 0.0)
+    poisonM = np.where(valid, gM, np.nan)
+    poisonK = np.where(valid, gK, np.inf)
+
+    def contract(Fs, G):
+        ops = [F[i] for F, i in zip(Fs, idx)]                             # [rows, Q, S] each
+        Gs = G.reshape([len(rows)] + [S] * d)
+        if d == 2:
+            return np.einsum("ras,rbt,rst->rab", *ops, Gs).reshape(len(rows), -1)
+        return np.einsum("ras,rbt,rcu,rstu->rabc", *ops, Gs).reshape(len(rows), -1)
+
+    dc, da = oa.adjoint(p, n_el, tabs, poisonM, poisonK)
+    ac, aa = oa.adjoint(p, n_el, tabs, poisonM, poisonK, absolute=True)
+    want_c = contract(FM, gM)
+    want_ac = contract([np.abs(F) for F in FM], np.abs(gM))
+    scale = np.abs(want_ac).max()
+    np.testing.assert_allclose(dc, want_c, rtol=0, atol=1e-14 * scale)
+    np.testing.assert_allclose(ac, want_ac, rtol=0, atol=1e-14 * scale)
+    for kk in range(d):
+        Fs = [FK[k] if k == kk else FM[k] for k in range(d)]
+        want = contract(Fs, gK)
+        want_abs = contract([np.abs(F) for F in Fs], np.abs(gK))
+        scale = np.abs(want_abs).max()
+        np.testing.assert_allclose(da[kk], want, rtol=0, atol=1e-14 * scale)
+        np.testing.assert_allclose(aa[kk], want_abs, rtol=0, atol=1e-14 * scale)
+        assert np.all(aa[kk] >= np.abs(da[kk]) * (1 - 1e-14))
+    # mass factors are non-negative (positive weights, B >= 0): for G >= 0 the two agree
+    gpos = np.abs(gM)
+    d1, _ = oa.adjoint(p, n_el, tabs, gpos, None)
+    a1, _ = oa.adjoint(p, n_el, tabs, gpos, None, absolute=True)
+    np.testing.assert_allclose(a1, d1, rtol=1e-14, atol=0)
