@@ -3,8 +3,8 @@
 One step = one pass of the whole path over the workload: the fused mass + stiffness
 forward assembly followed by its adjoint, on the 3D C^2 cubic space with 160^3
 elements (4,330,747 rows, 343 slots per row), random-Fourier c and anisotropic
-diagonal A, FP32 values in the implicit-column band layout, compensated final pass
-(FP64 accumulator).  Inputs (coefficients and upstream gradients) are resident in HBM
+diagonal A, FP32 values in the implicit-column band layout, the final directional pass
+accumulated in FP64 (the all-FP32 compensated Dot2 pass is timed beside it).  Inputs (coefficients and upstream gradients) are resident in HBM
 before timing; outputs are preallocated.
 
 value = slots processed per second over the step: 2 x rows x 343 assembled (M and K)
@@ -35,7 +35,7 @@ P, NEL = 3, (160, 160, 160)
 SEED_FAMILY = 5                # seeds of the 160^3 workload's Fourier fields and upstream gradients
 METRIC = "assembled nnz/s (3D C2 cubic M+K) FP32 vs FP64 at stated err; adjoint nnz/s"
 MODES = (("plain", 0), ("dot2", 1), ("f64_accumulate", 2))
-HEADLINE_MODE = 2              # compensated final pass through an FP64 accumulator
+HEADLINE_MODE = 2              # final pass accumulated in FP64 (mixed precision; every other stage FP32)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_160cubed.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1710_01048_amd", "csrc", "wqa_kernels.hip")
 
@@ -272,8 +272,9 @@ def rowscaled(got, want):
     return float((np.abs(got - want) / s).max())
 
 
-def normwise(got, want):
-    return float(np.abs(got - want).max() / np.abs(want).max())
+def per_entry(got, want, scale):
+    """Largest gradient error over the sum of the magnitudes of the terms the entry sums."""
+    return float((np.abs(got - want) / np.where(scale == 0, 1, scale)).max())
 
 
 def traffic_for(kernel):
@@ -411,8 +412,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "3D C2 cubic, 160^3 elements (4,330,747 rows x 343 slots), fused M+K forward "
-                               "then adjoint, random-Fourier c and diagonal A, FP32 with compensated final pass "
-                               "(FP64 accumulator)",
+                               "then adjoint, random-Fourier c and diagonal A, FP32 values and stages; the final "
+                               "directional pass accumulated in FP64 (Dot2-compensated FP32 pass reported beside it)",
+                   "final_pass": "f64_accumulate",
                    "rows": sp.n_rows, "slots_per_row": sp.slots_per_row, "nnz_per_step": nnz_step,
                    "parallelism": "single GPU"},
         "forward_ms": r32["fwd_ms"],
@@ -452,11 +454,17 @@ def main():
         for name, (Mg, Kg) in mode_rows.items():
             acc[f"fp32_{name}"] = {"M_rowscaled": rowscaled(Mg, Mw), "K_rowscaled": rowscaled(Kg, Kw)}
         wc32, wa32 = oa.adjoint(P, NEL, tabs, *g32[0], rows=sample.rows)
-        acc["fp32_grad_normwise"] = max(normwise(g, w) for g, w in zip(g32[1], [wc32] + list(wa32)))
+        sc32, sa32 = oa.adjoint(P, NEL, tabs, *g32[0], rows=sample.rows, absolute=True)
+        acc["fp32_grad_per_entry"] = max(per_entry(g, w, sc) for g, w, sc in
+                                         zip(g32[1], [wc32] + list(wa32), [sc32] + list(sa32)))
         if m64 is not None:
+            sc, sa = oa.adjoint(P, NEL, tabs, *up, rows=sample.rows, absolute=True)
             acc["fp64"] = {"M_rowscaled": rowscaled(m64[0], Mw), "K_rowscaled": rowscaled(m64[1], Kw),
-                           "grad_normwise": max(normwise(g, w) for g, w in zip(g64[1], [wc] + list(wa)))}
-        acc["tolerance"] = {"fp32": 1e-5, "fp64": 1e-12, "measure": "row-scaled (matrices), normwise (gradients)"}
+                           "grad_per_entry": max(per_entry(g, w, x) for g, w, x in
+                                                 zip(g64[1], [wc] + list(wa), [sc] + list(sa)))}
+        acc["tolerance"] = {"fp32": 1e-5, "fp64": 1e-12,
+                            "measure": "row-scaled (matrices); gradients per entry, over the sum of the "
+                                       "magnitudes of the terms each entry sums"}
         line["accuracy_vs_oracle"] = acc
     print(json.dumps(line), flush=True)
 

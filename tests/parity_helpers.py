@@ -88,7 +88,34 @@ def oracle_forward(p, n_el, rows, recipe, want_m=True, want_k=True):
     return M, K
 
 
-def normwise_error(got, want):
+def oracle_adjoint(p, n_el, tabs, gM, gK, rows):
+    """The oracle's gradients of the listed rows and, in the same layout, the scale of
+    each entry: the sum of the magnitudes of the terms it sums (``absolute=True``).
+    Returns ([dc, da_1..da_d], [scale_c, scale_1..scale_d]) with None left out."""
+    wc, wa = oa.adjoint(p, n_el, tabs, gM, gK, rows=rows)
+    sc, sa = oa.adjoint(p, n_el, tabs, gM, gK, rows=rows, absolute=True)
+    want = ([wc] if wc is not None else []) + (list(wa) if wa is not None else [])
+    scale = ([sc] if sc is not None else []) + (list(sa) if sa is not None else [])
+    return want, scale
+
+
+def entry_error(got, want, scale):
+    """Largest error of any single gradient entry relative to the sum of the magnitudes
+    of the terms that entry sums: max |got - want| / sum_s |G_s prod_k T_k|.  Entries
+    whose terms are all zero (zero-weight nodes) must come out exactly as the oracle's."""
     got = np.asarray(got, dtype=np.float64)
     want = np.asarray(want, dtype=np.float64)
-    return float(np.abs(got - want).max() / max(np.abs(want).max(), 1e-300))
+    scale = np.asarray(scale, dtype=np.float64)
+    diff = np.abs(got - want)
+    if np.any(~np.isfinite(got)):
+        return float("inf")
+    zero = scale == 0
+    if np.any(diff[zero] != 0):
+        return float("inf")
+    return float((diff[~zero] / scale[~zero]).max()) if (~zero).any() else 0.0
+
+
+def entry_errors(got, want, scale):
+    """entry_error of each field in turn (lists of arrays)."""
+    assert len(got) == len(want) == len(scale)
+    return [entry_error(g, w, s) for g, w, s in zip(got, want, scale)]
