@@ -111,6 +111,10 @@ class Space:
     def set_final_mode(self, mode):
         check(lib.wqa_set_final_mode(self._ctx, int(mode)))
 
+    def set_dispatch_limit(self, max_tasks):
+        """Wave tasks per kernel dispatch (0: the default); larger launches are split."""
+        check(lib.wqa_set_dispatch_limit(self._ctx, int(max_tasks)))
+
     # --- buffers ------------------------------------------------------------------------
     def _field(self, t, name, dtype=None):
         if not isinstance(t, torch.Tensor) or t.device != self.device:
@@ -255,6 +259,7 @@ class WQAssemble(torch.autograd.Function):
     @staticmethod
     def forward(ctx, space, c, *a):
         ctx.space = space
+        ctx.shapes = (c.shape,) + tuple(x.shape for x in a)     # grid-shaped or flat
         c = c.contiguous()
         a = [x.contiguous() for x in a]
         M, K = space.assemble_fused(c, a)
@@ -268,4 +273,7 @@ class WQAssemble(torch.autograd.Function):
         if gM is None and gK is None:
             return (None, None) + (None,) * space.dim
         dc, da = space.adjoint(gM, gK)
-        return (None, dc) + (tuple(da) if da is not None else (None,) * space.dim)
+        # gradients take the shape each input had
+        dc = None if dc is None else dc.view(ctx.shapes[0])
+        da = (None,) * space.dim if da is None else tuple(g.view(s) for g, s in zip(da, ctx.shapes[1:]))
+        return (None, dc) + da
