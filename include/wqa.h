@@ -69,15 +69,19 @@ typedef enum wqa_dtype { WQA_F32 = 0, WQA_F64 = 1 } wqa_dtype;
 typedef enum wqa_kind { WQA_MASS = 0, WQA_STIFFNESS = 1 } wqa_kind;
 
 /* How the last directional contraction (the final pass, over the first direction)
- * accumulates in the FP32 mode; every other stage accumulates in FP32.  FP64 calls
- * always accumulate in FP64.  Both compensated variants return the sum as if it had
- * been computed in at least twice the working precision and rounded once. */
+ * accumulates in the FP32 mode; every other stage accumulates in FP32 and every input,
+ * output and intermediate stays FP32.  FP64 calls always accumulate in FP64.  Both
+ * non-plain variants return the final pass's sum as if it had been computed in at
+ * least twice the working precision and rounded once to FP32. */
 typedef enum wqa_final {
     WQA_FINAL_PLAIN = 0,  /* FP32 fused multiply-adds */
-    WQA_FINAL_DOT2 = 1,   /* compensated in FP32 registers: error-free products (FMA) and
-                             error-free sums, errors summed apart (Ogita, Rump, Oishi) */
-    WQA_FINAL_F64 = 2     /* compensated through an FP64 accumulator: every product of FP32
-                             values is exact in FP64, sums round at 2^-53 (default) */
+    WQA_FINAL_DOT2 = 1,   /* compensated summation in FP32 registers: error-free products
+                             (FMA) and error-free sums, the errors summed apart and added
+                             once (Ogita, Rump, Oishi's Dot2) */
+    WQA_FINAL_F64 = 2     /* mixed precision, not compensated: each FP32 stage result is
+                             multiplied by the FP64 table entry of the first direction and
+                             the products are summed in an FP64 register, rounded once to
+                             FP32 (default; products and sums round at 2^-53) */
 } wqa_final;
 
 /* Returns WQA_ABI_VERSION of the loaded library. */
@@ -133,11 +137,19 @@ wqa_status wqa_set_default_rules(wqa_ctx *ctx);
  * validated: nodes with nonzero weight lie strictly inside supp(B_j) and at least
  * 1e-9 element widths from any knot, and the relative exactness residual over the
  * interacting columns is <= exact_tol (WQA_ERULE otherwise, nothing installed).
- * exact_tol < 0 skips validation.  Nodes in FP64 parametric units carry up to
+ * exact_tol < 0 skips validation.  Any order of a row's nodes is accepted (the grid
+ * coordinates follow it); the kernels skip table entries that vanish for rules with one
+ * node per support element in order, and take the full loops in a direction whose
+ * rules break that pattern.  Nodes in FP64 parametric units carry up to
  * n_elem * 2^-53 element widths of rounding, so no rule shows a residual much below
  * that on long directions (wqa_set_default_rules validates its own rules against
  * max(1e-12, 8 n_elem 2^-53)).  Copies the arrays; uploads the tables to the device of
- * a device context. */
+ * a device context.
+ *
+ * Ordering: the calls that change rules or knots (wqa_set_rules, wqa_set_default_rules,
+ * wqa_set_space, wqa_set_knots followed by either) wait for every kernel queued on the
+ * context's device, on any stream, before they touch the device tables; work queued
+ * before such a call uses the old rules, work queued after it the new ones. */
 wqa_status wqa_set_rules(wqa_ctx *ctx, wqa_kind kind, int dir, int q,
                          const double *nodes, const double *weights, double exact_tol);
 
@@ -158,6 +170,14 @@ wqa_status wqa_query(const wqa_ctx *ctx, int64_t *n_rows, int64_t *slots_per_row
 
 /* Selects how FP32 calls accumulate the final directional pass (default WQA_FINAL_F64). */
 wqa_status wqa_set_final_mode(wqa_ctx *ctx, wqa_final mode);
+
+/* Caps the wave tasks (tiles of consecutive rows) one kernel dispatch takes: launches
+ * with more are queued as several dispatches on the same stream, with identical
+ * results.  0 restores the default, 2^24 tasks, which keeps every dispatch below HIP's
+ * 32-bit work-item count whatever the space (a 2D quadratic space of 2^24 x 64 elements
+ * needs about 10^8 tasks); larger values are clamped to it.  WQA_EINVAL for negative
+ * values. */
+wqa_status wqa_set_dispatch_limit(wqa_ctx *ctx, int64_t max_tasks);
 
 /* Mass matrix (eq:Mass with the folded coefficient c).  c: device [N_1..N_d] of dtype
  * on the all-mass grid; M: device [rows][S^d] of dtype (fully overwritten). */

@@ -546,6 +546,9 @@ struct wqa_ctx {
     std::vector<double> tab64[2][wqa::kMaxDim];
     std::vector<float> tab32[2][wqa::kMaxDim];
     bool have_rule[2][wqa::kMaxDim] = {};
+    // the rows at least p from both ends have tables that vanish outside q <= s <= q + p
+    bool banded[2][wqa::kMaxDim] = {};
+    int64_t max_tasks = wqa::kMaxTasksPerDispatch;      // wave tasks per kernel dispatch
     // device copies
     void *dev = nullptr;
     size_t dev_bytes = 0;
@@ -622,6 +625,18 @@ void build_table(wqa_ctx *c, int kind, int dir) {
                 }
             }
     });
+    // The kernels skip the entries outside q <= s <= q + p of rows at least p from both
+    // ends; that holds when node q of each such row lies in element q of its support (the
+    // library's rules), so it is checked on the built table rather than assumed.
+    bool banded = true;
+    for (int64_t j = p; j < n - p && banded; ++j)
+        for (int q = 0; q < Q && banded; ++q)
+            for (int s = 0; s < S; ++s)
+                if ((s < q || s > q + p) && T[(j * Q + q) * S + s] != 0.0) {
+                    banded = false;
+                    break;
+                }
+    c->banded[kind][dir] = banded;
 }
 
 wqa_status upload(wqa_ctx *c) {
@@ -633,9 +648,15 @@ wqa_status upload(wqa_ctx *c) {
         for (int k = 0; k < c->dim; ++k) need += (size_t)c->n[k] * Q * S * (8 + 4) + 512;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return fail(WQA_EHIP, "hipSetDevice(%d): %s", c->device, hipGetErrorString(e));
+    // Kernels queued earlier on any stream may still read the tables: wait for the device
+    // before they are rewritten in place or freed.
+    if (c->dev) {
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return fail(WQA_EHIP, "waiting for queued kernels before a table upload: %s",
+                                         hipGetErrorString(e));
+    }
     if (need > c->dev_bytes) {
         if (c->dev) {
-            (void)hipDeviceSynchronize();
             (void)hipFree(c->dev);
             c->dev = nullptr;
             c->dev_bytes = 0;
@@ -1001,6 +1022,14 @@ wqa_status wqa_set_final_mode(wqa_ctx *c, wqa_final mode) {
     return ok();
 }
 
+wqa_status wqa_set_dispatch_limit(wqa_ctx *c, int64_t max_tasks) {
+    if (!c) return fail(WQA_EINVAL, "wqa_set_dispatch_limit: NULL context");
+    if (max_tasks < 0) return fail(WQA_EINVAL, "wqa_set_dispatch_limit: %lld tasks", (long long)max_tasks);
+    c->max_tasks = max_tasks == 0 ? wqa::kMaxTasksPerDispatch
+                                  : std::min<int64_t>(max_tasks, wqa::kMaxTasksPerDispatch);
+    return ok();
+}
+
 }  // extern "C"
 
 namespace {
@@ -1021,6 +1050,9 @@ wqa_status ready(wqa_ctx *c, const char *who, wqa_dtype dtype) {
 void fill(const wqa_ctx *c, wqa::DevSpace &sp, wqa::DevTabs &tb, wqa_dtype dtype) {
     sp.d = c->dim;
     sp.p = c->p;
+    sp.band = 0;
+    for (int k = 0; k < c->dim; ++k)
+        if (c->banded[WQA_MASS][k] && c->banded[WQA_STIFFNESS][k]) sp.band |= 1 << k;
     for (int k = 0; k < wqa::kMaxDim; ++k) {
         sp.n[k] = c->n[k];
         sp.N[k] = c->N[k];
@@ -1052,7 +1084,7 @@ wqa_status forward(wqa_ctx *c, const char *who, wqa_dtype dtype, int what, const
     wqa::DevTabs tb;
     fill(c, sp, tb, dtype);
     hipError_t e = wqa::launch_forward((int)dtype, c->final_mode, what, sp, tb, cf, a, M, K,
-                                       (hipStream_t)stream);
+                                       (hipStream_t)stream, c->max_tasks);
     if (e != hipSuccess) return fail(WQA_EHIP, "%s: kernel launch: %s", who, hipGetErrorString(e));
     return ok();
 }
@@ -1075,7 +1107,8 @@ wqa_status apply(wqa_ctx *c, const char *who, wqa_dtype dtype, int what, bool on
     wqa::DevSpace sp;
     wqa::DevTabs tb;
     fill(c, sp, tb, dtype);
-    hipError_t e = wqa::launch_apply((int)dtype, what, ones, sp, tb, cf, a, x, y, (hipStream_t)stream);
+    hipError_t e = wqa::launch_apply((int)dtype, what, ones, sp, tb, cf, a, x, y, (hipStream_t)stream,
+                                     c->max_tasks);
     if (e != hipSuccess) return fail(WQA_EHIP, "%s: kernel launch: %s", who, hipGetErrorString(e));
     return ok();
 }
@@ -1131,7 +1164,7 @@ wqa_status wqa_assemble_adjoint(wqa_ctx *c, wqa_dtype dtype, const void *gM, con
     wqa::DevTabs tb;
     fill(c, sp, tb, dtype);
     hipError_t e = wqa::launch_adjoint((int)dtype, c->final_mode, what, sp, tb, gM, gK, dc, da,
-                                       (hipStream_t)stream);
+                                       (hipStream_t)stream, c->max_tasks);
     if (e != hipSuccess) return fail(WQA_EHIP, "%s: kernel launch: %s", who, hipGetErrorString(e));
     return ok();
 }

@@ -14,9 +14,15 @@ enum What { kWhatM = 1, kWhatK = 2, kWhatMK = 3 };
 // Sizes of the tensor-product space as the kernels see them.
 struct DevSpace {
     int d, p;
+    int band;             // bit k: every row at least p from both ends of direction k has
+                          // tables (both kinds) that vanish outside q <= s <= q + p
     int64_t n[kMaxDim];   // basis functions per direction
     int64_t N[kMaxDim];   // grid points per direction (n * (p + 1))
 };
+
+// Largest number of wave tasks one kernel dispatch takes by default; larger launches
+// are split into several dispatches (HIP's grid size is counted in work-items, 32 bits).
+constexpr int64_t kMaxTasksPerDispatch = int64_t(1) << 24;
 
 // Contraction tables T[kind][dir] laid out [n_dir][Q][S] on the device, in the call's
 // dtype, plus FP64 copies for the FP64-accumulated final pass.
@@ -26,18 +32,20 @@ struct DevTabs {
 };
 
 // Forward assembly (mass, stiffness or both).  dtype 0 = FP32, 1 = FP64.
+// max_tasks: wave tasks per dispatch (launches with more are split).
 hipError_t launch_forward(int dtype, int final_mode, int what, const DevSpace &sp,
                           const DevTabs &tb, const void *c, const void *const *a,
-                          void *M, void *K, hipStream_t stream);
+                          void *M, void *K, hipStream_t stream, int64_t max_tasks);
 
 // Adjoint (either or both upstream gradients).
 hipError_t launch_adjoint(int dtype, int final_mode, int what, const DevSpace &sp,
                           const DevTabs &tb, const void *gM, const void *gK,
-                          void *dc, void *const *da, hipStream_t stream);
+                          void *dc, void *const *da, hipStream_t stream, int64_t max_tasks);
 
 // Matrix-free product y = M x (what = kWhatM, coefficient c) or y = K x (kWhatK,
 // coefficients a), or with ones = true the load vector y_i = integral c B_i (x unused).
 hipError_t launch_apply(int dtype, int what, bool ones, const DevSpace &sp, const DevTabs &tb,
-                        const void *c, const void *const *a, const void *x, void *y, hipStream_t stream);
+                        const void *c, const void *const *a, const void *x, void *y, hipStream_t stream,
+                        int64_t max_tasks);
 
 }  // namespace wqa

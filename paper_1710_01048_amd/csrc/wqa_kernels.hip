@@ -29,6 +29,8 @@
 //     pass; adjoint terms with the mass table in direction d share the first pass.
 #include "wqa_internal.h"
 
+#include <algorithm>
+
 namespace wqa {
 namespace {
 
@@ -143,10 +145,13 @@ __device__ __forceinline__ cptr<T> fresh(cptr<T> p) {
     return p;
 }
 
-// Rows whose nodes sit one per element of their support (every row but the p at each
-// end of a direction) have tables that vanish outside q <= s <= q + P: node q only
-// meets the P+1 functions living on its element.  The banded code paths skip those
-// zeros; the others run the full Q x S loops.  Both give bitwise the same sums.
+// Rows whose nodes sit one per element of their support, in order (every row but the p
+// at each end of a direction, with the library's rules) have tables that vanish outside
+// q <= s <= q + P: node q only meets the P+1 functions living on its element.  The
+// banded code paths skip those zeros; the others run the full Q x S loops.  Both give
+// bitwise the same sums.  The host checks the built tables and clears a direction's bit
+// in DevSpace::band when a caller's rule breaks the pattern; tiles then take the full
+// loops.
 template <int P>
 __device__ __forceinline__ constexpr bool in_band(int q, int s) {
     return s >= q && s <= q + P;
@@ -193,17 +198,18 @@ struct Tile {
 enum LineSet { kLinesAll = 0, kLinesInterior = 1, kLinesBoundary = 2 };
 
 // Line l of a set, enumerated in row order, as its index among all lines
-// ((i_1 n_2) + i_2 for d = 3, i_1 for d = 2).
-template <int D, int P, int LS>
-__device__ __forceinline__ int64_t line_of(const DevSpace &sp, int64_t l) {
-    if constexpr (LS == kLinesAll) return l;
+// ((i_1 n_2) + i_2 for d = 3, i_1 for d = 2).  ls is a compile-time constant in every
+// kernel but the adjoint's non-banded one.
+template <int D, int P>
+__device__ __forceinline__ int64_t line_of(const DevSpace &sp, int64_t l, int ls) {
+    if (ls == kLinesAll) return l;
     const int64_t n0 = sp.n[0];
     if constexpr (D == 2) {
-        if constexpr (LS == kLinesInterior) return P + l;
+        if (ls == kLinesInterior) return P + l;
         else return l < P ? l : n0 - 2 * P + l;
     } else {
         const int64_t n1 = sp.n[1];
-        if constexpr (LS == kLinesInterior) {
+        if (ls == kLinesInterior) {
             const int64_t w = n1 - 2 * P, a = l / w;
             return (P + a) * n1 + P + (l - a * w);
         } else {
@@ -218,13 +224,13 @@ __device__ __forceinline__ int64_t line_of(const DevSpace &sp, int64_t l) {
     }
 }
 
-template <int D, int P, int LS>
+template <int D, int P>
 __device__ __forceinline__ Tile make_tile(const DevSpace &sp, int64_t task, int tiles_per_line, int R,
-                                          int lanes_per_row, int lane) {
+                                          int lanes_per_row, int lane, int ls) {
     Tile t;
     const int64_t l = task / tiles_per_line;
     const int tile = (int)(task - l * tiles_per_line);
-    const int64_t line = line_of<D, P, LS>(sp, l);
+    const int64_t line = line_of<D, P>(sp, l, ls);
     t.nl = sp.n[D - 1];
     if constexpr (D == 3) {
         t.i1 = line / sp.n[1];
@@ -243,11 +249,12 @@ __device__ __forceinline__ Tile make_tile(const DevSpace &sp, int64_t task, int 
     return t;
 }
 
-// Whether every leading index of the tile's line is interior (banded leading tables).
+// Whether every leading index of the tile's line is interior and its direction's tables
+// banded (see in_band).
 template <int D, int P>
 __device__ __forceinline__ bool tile_banded(const DevSpace &sp, const Tile &t) {
-    bool b = t.i1 >= P && t.i1 < sp.n[0] - P;
-    if constexpr (D == 3) b = b && t.i2 >= P && t.i2 < sp.n[1] - P;
+    bool b = (sp.band & 1) && t.i1 >= P && t.i1 < sp.n[0] - P;
+    if constexpr (D == 3) b = b && (sp.band & 2) && t.i2 >= P && t.i2 < sp.n[1] - P;
     return b;
 }
 
@@ -480,7 +487,7 @@ template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int R>
 __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     DevSpace sp, DevTabs tb, const T *__restrict__ cf, const T *__restrict__ a0,
     const T *__restrict__ a1, const T *__restrict__ a2, T *__restrict__ Mo,
-    T *__restrict__ Ko, int64_t n_tasks, int tiles_per_line) {
+    T *__restrict__ Ko, int64_t task0, int64_t n_tasks, int tiles_per_line) {
     constexpr int S = 2 * P + 1;                   // R: rows per wave tile (<= 64 / S)
     constexpr int SL = (D == 3) ? S * S : S;
     constexpr int Q = P + 1, NG = (D == 3) ? Q * Q : Q;
@@ -489,9 +496,9 @@ __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     __shared__ __align__(16) T stage[WPB][OUT > IN ? OUT : IN];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t task = (int64_t)block_grouped<8>() * WPB + wave;
+    const int64_t task = task0 + (int64_t)block_grouped<8>() * WPB + wave;
     if (task >= n_tasks) return;                   // whole wave leaves; no block barriers below
-    const Tile t = make_tile<D, P, kLinesAll>(sp, task, tiles_per_line, R, S, lane);
+    const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, S, lane, kLinesAll);
     if (tile_banded<D, P>(sp, t))
         forward_body<T, P, D, WHAT, FINAL, true, R>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
     else
@@ -912,20 +919,23 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
     }
 }
 
+// INTERIOR: the banded kernel over the interior lines.  Otherwise the full loops over
+// the lines of line_set (the boundary lines, or every line when some leading direction's
+// tables are not banded).
 template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int RING, bool INTERIOR>
 __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
     DevSpace sp, DevTabs tb, const T *__restrict__ gM, const T *__restrict__ gK,
     T *__restrict__ dc, T *__restrict__ da0, T *__restrict__ da1, T *__restrict__ da2,
-    int64_t n_tasks, int tiles_per_line) {
+    int64_t task0, int64_t n_tasks, int tiles_per_line, int line_set) {
     constexpr int Q = P + 1;
     constexpr int R = 64 / Q;                      // rows per wave tile
     using A = Adjoint<T, P, D, FINAL, false, WPB, R, RING>;
     __shared__ __align__(16) uint32_t ring[WPB][RING * A::SLOT];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t task = (int64_t)block_chunked() * WPB + wave;
+    const int64_t task = task0 + (int64_t)block_chunked() * WPB + wave;
     if (task >= n_tasks) return;
-    const Tile t = make_tile<D, P, INTERIOR ? kLinesInterior : kLinesBoundary>(sp, task, tiles_per_line, R, Q, lane);
+    const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, Q, lane, INTERIOR ? (int)kLinesInterior : line_set);
     adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING>(sp, tb, t, ring[wave], lane, gM, gK, dc, da0, da1,
                                                               da2);
 }
@@ -1092,15 +1102,16 @@ template <typename T, int P, int D, int WHAT, bool ONES>
 __global__ __launch_bounds__(64 * kApplyWaves, sizeof(T) == 4 ? 4 : 2) void apply_kernel(DevSpace sp, DevTabs tb, const T *__restrict__ cf,
                                                     const T *__restrict__ a0, const T *__restrict__ a1,
                                                     const T *__restrict__ a2, const T *__restrict__ x,
-                                                    T *__restrict__ y, int64_t n_tasks, int tiles_per_line) {
+                                                    T *__restrict__ y, int64_t task0, int64_t n_tasks,
+                                                    int tiles_per_line) {
     constexpr int WPB = kApplyWaves, Q = P + 1, S = 2 * P + 1, R = 64 / Q;
     constexpr int W = R + 2 * P, NL = (D == 3) ? S * S : S;
     __shared__ __align__(16) T win[WPB][ONES ? 1 : NL * W];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t task = (int64_t)blockIdx.x * WPB + wave;
+    const int64_t task = task0 + (int64_t)blockIdx.x * WPB + wave;
     if (task >= n_tasks) return;
-    const Tile t = make_tile<D, P, kLinesAll>(sp, task, tiles_per_line, R, Q, lane);
+    const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, Q, lane, kLinesAll);
     if constexpr (!ONES) {
         const int64_t n0 = sp.n[0], n1 = (D == 3) ? sp.n[1] : 1, nl = t.nl;
         for (int e = lane; e < NL * W; e += 64) {
@@ -1138,9 +1149,23 @@ void line_sets(const DevSpace &sp, int64_t &interior, int64_t &boundary) {
     boundary = all - in;
 }
 
+// Launches kernel(task0, n_tasks) over [0, tasks) in dispatches of at most max_tasks
+// tasks (a multiple of wpb), so that no grid passes HIP's 32-bit work-item count.
+template <class L>
+hipError_t split_launch(int64_t tasks, int64_t max_tasks, int wpb, L launch) {
+    const int64_t step = std::max<int64_t>(wpb, max_tasks / wpb * wpb);
+    for (int64_t t0 = 0; t0 < tasks; t0 += step) {
+        const int64_t here = std::min(step, tasks - t0);
+        launch(t0, dim3((unsigned)((here + wpb - 1) / wpb)));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <typename T, int P, int D, int WHAT, int FINAL>
 hipError_t run_forward(const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a,
-                       void *M, void *K, hipStream_t st) {
+                       void *M, void *K, hipStream_t st, int64_t max_tasks) {
     constexpr int S = 2 * P + 1, R = 64 / S;
     // one wave per work-group: the same occupancy as larger groups (set by registers and
     // the whole-tile LDS staging), but finer-grained dispatch; measured 6-9% faster than
@@ -1156,14 +1181,16 @@ hipError_t run_forward(const DevSpace &sp, const DevTabs &tb, const void *c, con
         a1 = (const T *)a[1];
         a2 = D == 3 ? (const T *)a[2] : nullptr;
     }
-    hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, WPB, R>), dim3((unsigned)((tasks + WPB - 1) / WPB)),
-                       dim3(64 * WPB), 0, st, sp, tb, (const T *)c, a0, a1, a2, (T *)M, (T *)K, tasks, tiles);
-    return hipGetLastError();
+    return split_launch(tasks, max_tasks, WPB, [&](int64_t t0, dim3 grid) {
+        const int64_t end = t0 + (int64_t)grid.x * WPB < tasks ? t0 + (int64_t)grid.x * WPB : tasks;
+        hipLaunchKernelGGL((forward_kernel<T, P, D, WHAT, FINAL, WPB, R>), grid, dim3(64 * WPB), 0, st, sp, tb,
+                           (const T *)c, a0, a1, a2, (T *)M, (T *)K, t0, end, tiles);
+    });
 }
 
 template <typename T, int P, int D, int WHAT, int FINAL>
 hipError_t run_adjoint(const DevSpace &sp, const DevTabs &tb, const void *gM, const void *gK,
-                       void *dc, void *const *da, hipStream_t st) {
+                       void *dc, void *const *da, hipStream_t st, int64_t max_tasks) {
     constexpr int Q = P + 1, R = 64 / Q;
     // ring depth: FP32 4 slabs, FP64 3 slabs (a 2-slab ring measured 1.5% slower in FP32);
     // one wave per work-group (as fast as four in FP32, 10% faster than two in FP64)
@@ -1172,6 +1199,15 @@ hipError_t run_adjoint(const DevSpace &sp, const DevTabs &tb, const void *gM, co
     const int tiles = (int)((sp.n[D - 1] + R - 1) / R);
     int64_t lines[2];
     line_sets<D, P>(sp, lines[0], lines[1]);
+    // every leading direction banded: the banded kernel takes the interior lines and the
+    // other kernel the rest; else the other kernel takes every line
+    const int lead = (1 << (D - 1)) - 1;
+    const bool banded = (sp.band & lead) == lead;
+    if (!banded) {
+        lines[1] += lines[0];
+        lines[0] = 0;
+    }
+    const int other_set = banded ? (int)kLinesBoundary : (int)kLinesAll;
     T *d0 = nullptr, *d1 = nullptr, *d2 = nullptr;
     if (WHAT & kWhatK) {
         d0 = (T *)da[0];
@@ -1181,14 +1217,18 @@ hipError_t run_adjoint(const DevSpace &sp, const DevTabs &tb, const void *gM, co
     for (int set = 0; set < 2; ++set) {
         const int64_t tasks = lines[set] * tiles;
         if (tasks == 0) continue;
-        const dim3 grid((unsigned)((tasks + WPB - 1) / WPB)), block(64 * WPB);
-        if (set == 0)
-            hipLaunchKernelGGL((adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, true>), grid, block, 0, st, sp, tb,
-                               (const T *)gM, (const T *)gK, (T *)dc, d0, d1, d2, tasks, tiles);
-        else
-            hipLaunchKernelGGL((adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, false>), grid, block, 0, st, sp,
-                               tb, (const T *)gM, (const T *)gK, (T *)dc, d0, d1, d2, tasks, tiles);
-        const hipError_t e = hipGetLastError();
+        const dim3 block(64 * WPB);
+        const hipError_t e = split_launch(tasks, max_tasks, WPB, [&](int64_t t0, dim3 grid) {
+            const int64_t end = t0 + (int64_t)grid.x * WPB < tasks ? t0 + (int64_t)grid.x * WPB : tasks;
+            if (set == 0)
+                hipLaunchKernelGGL((adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, true>), grid, block, 0, st, sp,
+                                   tb, (const T *)gM, (const T *)gK, (T *)dc, d0, d1, d2, t0, end, tiles,
+                                   (int)kLinesInterior);
+            else
+                hipLaunchKernelGGL((adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, false>), grid, block, 0, st, sp,
+                                   tb, (const T *)gM, (const T *)gK, (T *)dc, d0, d1, d2, t0, end, tiles,
+                                   other_set);
+        });
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1196,7 +1236,7 @@ hipError_t run_adjoint(const DevSpace &sp, const DevTabs &tb, const void *gM, co
 
 template <typename T, int P, int D, int WHAT, bool ONES>
 hipError_t run_apply(const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a, const void *x,
-                     void *y, hipStream_t st) {
+                     void *y, hipStream_t st, int64_t max_tasks) {
     constexpr int Q = P + 1, R = 64 / Q, WPB = kApplyWaves;
     const int tiles = (int)((sp.n[D - 1] + R - 1) / R);
     int64_t lines = 1;
@@ -1208,115 +1248,119 @@ hipError_t run_apply(const DevSpace &sp, const DevTabs &tb, const void *c, const
         a1 = (const T *)a[1];
         a2 = D == 3 ? (const T *)a[2] : nullptr;
     }
-    hipLaunchKernelGGL((apply_kernel<T, P, D, WHAT, ONES>), dim3((unsigned)((tasks + WPB - 1) / WPB)), dim3(64 * WPB),
-                       0, st, sp, tb, (const T *)c, a0, a1, a2, (const T *)x, (T *)y, tasks, tiles);
-    return hipGetLastError();
+    return split_launch(tasks, max_tasks, WPB, [&](int64_t t0, dim3 grid) {
+        const int64_t end = t0 + (int64_t)grid.x * WPB < tasks ? t0 + (int64_t)grid.x * WPB : tasks;
+        hipLaunchKernelGGL((apply_kernel<T, P, D, WHAT, ONES>), grid, dim3(64 * WPB), 0, st, sp, tb, (const T *)c,
+                           a0, a1, a2, (const T *)x, (T *)y, t0, end, tiles);
+    });
 }
 
 template <typename T, int P, int D>
 hipError_t apply_what(int what, bool ones, const DevSpace &sp, const DevTabs &tb, const void *c,
-                      const void *const *a, const void *x, void *y, hipStream_t st) {
-    if (ones) return run_apply<T, P, D, kWhatM, true>(sp, tb, c, a, x, y, st);
-    if (what == kWhatM) return run_apply<T, P, D, kWhatM, false>(sp, tb, c, a, x, y, st);
-    return run_apply<T, P, D, kWhatK, false>(sp, tb, c, a, x, y, st);
+                      const void *const *a, const void *x, void *y, hipStream_t st, int64_t max_tasks) {
+    if (ones) return run_apply<T, P, D, kWhatM, true>(sp, tb, c, a, x, y, st, max_tasks);
+    if (what == kWhatM) return run_apply<T, P, D, kWhatM, false>(sp, tb, c, a, x, y, st, max_tasks);
+    return run_apply<T, P, D, kWhatK, false>(sp, tb, c, a, x, y, st, max_tasks);
 }
 
 template <typename T>
 hipError_t apply_shape(int what, bool ones, const DevSpace &sp, const DevTabs &tb, const void *c,
-                       const void *const *a, const void *x, void *y, hipStream_t st) {
-    if (sp.p == 2 && sp.d == 2) return apply_what<T, 2, 2>(what, ones, sp, tb, c, a, x, y, st);
-    if (sp.p == 2 && sp.d == 3) return apply_what<T, 2, 3>(what, ones, sp, tb, c, a, x, y, st);
-    if (sp.p == 3 && sp.d == 2) return apply_what<T, 3, 2>(what, ones, sp, tb, c, a, x, y, st);
-    if (sp.p == 3 && sp.d == 3) return apply_what<T, 3, 3>(what, ones, sp, tb, c, a, x, y, st);
+                       const void *const *a, const void *x, void *y, hipStream_t st, int64_t max_tasks) {
+    if (sp.p == 2 && sp.d == 2) return apply_what<T, 2, 2>(what, ones, sp, tb, c, a, x, y, st, max_tasks);
+    if (sp.p == 2 && sp.d == 3) return apply_what<T, 2, 3>(what, ones, sp, tb, c, a, x, y, st, max_tasks);
+    if (sp.p == 3 && sp.d == 2) return apply_what<T, 3, 2>(what, ones, sp, tb, c, a, x, y, st, max_tasks);
+    if (sp.p == 3 && sp.d == 3) return apply_what<T, 3, 3>(what, ones, sp, tb, c, a, x, y, st, max_tasks);
     return hipErrorInvalidValue;
 }
 
 template <typename T, int P, int D, int WHAT>
 hipError_t fwd_final(int final_mode, const DevSpace &sp, const DevTabs &tb, const void *c,
-                     const void *const *a, void *M, void *K, hipStream_t st) {
+                     const void *const *a, void *M, void *K, hipStream_t st, int64_t max_tasks) {
     if constexpr (sizeof(T) == 8) {
-        return run_forward<T, P, D, WHAT, 0>(sp, tb, c, a, M, K, st);
+        return run_forward<T, P, D, WHAT, 0>(sp, tb, c, a, M, K, st, max_tasks);
     } else {
         switch (final_mode) {
-            case 0: return run_forward<T, P, D, WHAT, 0>(sp, tb, c, a, M, K, st);
-            case 1: return run_forward<T, P, D, WHAT, 1>(sp, tb, c, a, M, K, st);
-            default: return run_forward<T, P, D, WHAT, 2>(sp, tb, c, a, M, K, st);
+            case 0: return run_forward<T, P, D, WHAT, 0>(sp, tb, c, a, M, K, st, max_tasks);
+            case 1: return run_forward<T, P, D, WHAT, 1>(sp, tb, c, a, M, K, st, max_tasks);
+            default: return run_forward<T, P, D, WHAT, 2>(sp, tb, c, a, M, K, st, max_tasks);
         }
     }
 }
 
 template <typename T, int P, int D, int WHAT>
 hipError_t adj_final(int final_mode, const DevSpace &sp, const DevTabs &tb, const void *gM,
-                     const void *gK, void *dc, void *const *da, hipStream_t st) {
+                     const void *gK, void *dc, void *const *da, hipStream_t st, int64_t max_tasks) {
     if constexpr (sizeof(T) == 8) {
-        return run_adjoint<T, P, D, WHAT, 0>(sp, tb, gM, gK, dc, da, st);
+        return run_adjoint<T, P, D, WHAT, 0>(sp, tb, gM, gK, dc, da, st, max_tasks);
     } else {
         switch (final_mode) {
-            case 0: return run_adjoint<T, P, D, WHAT, 0>(sp, tb, gM, gK, dc, da, st);
-            case 1: return run_adjoint<T, P, D, WHAT, 1>(sp, tb, gM, gK, dc, da, st);
-            default: return run_adjoint<T, P, D, WHAT, 2>(sp, tb, gM, gK, dc, da, st);
+            case 0: return run_adjoint<T, P, D, WHAT, 0>(sp, tb, gM, gK, dc, da, st, max_tasks);
+            case 1: return run_adjoint<T, P, D, WHAT, 1>(sp, tb, gM, gK, dc, da, st, max_tasks);
+            default: return run_adjoint<T, P, D, WHAT, 2>(sp, tb, gM, gK, dc, da, st, max_tasks);
         }
     }
 }
 
 template <typename T, int P, int D>
 hipError_t fwd_what(int final_mode, int what, const DevSpace &sp, const DevTabs &tb, const void *c,
-                    const void *const *a, void *M, void *K, hipStream_t st) {
+                    const void *const *a, void *M, void *K, hipStream_t st, int64_t max_tasks) {
     switch (what) {
-        case kWhatM: return fwd_final<T, P, D, kWhatM>(final_mode, sp, tb, c, a, M, K, st);
-        case kWhatK: return fwd_final<T, P, D, kWhatK>(final_mode, sp, tb, c, a, M, K, st);
-        default: return fwd_final<T, P, D, kWhatMK>(final_mode, sp, tb, c, a, M, K, st);
+        case kWhatM: return fwd_final<T, P, D, kWhatM>(final_mode, sp, tb, c, a, M, K, st, max_tasks);
+        case kWhatK: return fwd_final<T, P, D, kWhatK>(final_mode, sp, tb, c, a, M, K, st, max_tasks);
+        default: return fwd_final<T, P, D, kWhatMK>(final_mode, sp, tb, c, a, M, K, st, max_tasks);
     }
 }
 
 template <typename T, int P, int D>
 hipError_t adj_what(int final_mode, int what, const DevSpace &sp, const DevTabs &tb, const void *gM,
-                    const void *gK, void *dc, void *const *da, hipStream_t st) {
+                    const void *gK, void *dc, void *const *da, hipStream_t st, int64_t max_tasks) {
     switch (what) {
-        case kWhatM: return adj_final<T, P, D, kWhatM>(final_mode, sp, tb, gM, gK, dc, da, st);
-        case kWhatK: return adj_final<T, P, D, kWhatK>(final_mode, sp, tb, gM, gK, dc, da, st);
-        default: return adj_final<T, P, D, kWhatMK>(final_mode, sp, tb, gM, gK, dc, da, st);
+        case kWhatM: return adj_final<T, P, D, kWhatM>(final_mode, sp, tb, gM, gK, dc, da, st, max_tasks);
+        case kWhatK: return adj_final<T, P, D, kWhatK>(final_mode, sp, tb, gM, gK, dc, da, st, max_tasks);
+        default: return adj_final<T, P, D, kWhatMK>(final_mode, sp, tb, gM, gK, dc, da, st, max_tasks);
     }
 }
 
 template <typename T>
 hipError_t fwd_shape(int final_mode, int what, const DevSpace &sp, const DevTabs &tb, const void *c,
-                     const void *const *a, void *M, void *K, hipStream_t st) {
-    if (sp.p == 2 && sp.d == 2) return fwd_what<T, 2, 2>(final_mode, what, sp, tb, c, a, M, K, st);
-    if (sp.p == 2 && sp.d == 3) return fwd_what<T, 2, 3>(final_mode, what, sp, tb, c, a, M, K, st);
-    if (sp.p == 3 && sp.d == 2) return fwd_what<T, 3, 2>(final_mode, what, sp, tb, c, a, M, K, st);
-    if (sp.p == 3 && sp.d == 3) return fwd_what<T, 3, 3>(final_mode, what, sp, tb, c, a, M, K, st);
+                     const void *const *a, void *M, void *K, hipStream_t st, int64_t max_tasks) {
+    if (sp.p == 2 && sp.d == 2) return fwd_what<T, 2, 2>(final_mode, what, sp, tb, c, a, M, K, st, max_tasks);
+    if (sp.p == 2 && sp.d == 3) return fwd_what<T, 2, 3>(final_mode, what, sp, tb, c, a, M, K, st, max_tasks);
+    if (sp.p == 3 && sp.d == 2) return fwd_what<T, 3, 2>(final_mode, what, sp, tb, c, a, M, K, st, max_tasks);
+    if (sp.p == 3 && sp.d == 3) return fwd_what<T, 3, 3>(final_mode, what, sp, tb, c, a, M, K, st, max_tasks);
     return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t adj_shape(int final_mode, int what, const DevSpace &sp, const DevTabs &tb, const void *gM,
-                     const void *gK, void *dc, void *const *da, hipStream_t st) {
-    if (sp.p == 2 && sp.d == 2) return adj_what<T, 2, 2>(final_mode, what, sp, tb, gM, gK, dc, da, st);
-    if (sp.p == 2 && sp.d == 3) return adj_what<T, 2, 3>(final_mode, what, sp, tb, gM, gK, dc, da, st);
-    if (sp.p == 3 && sp.d == 2) return adj_what<T, 3, 2>(final_mode, what, sp, tb, gM, gK, dc, da, st);
-    if (sp.p == 3 && sp.d == 3) return adj_what<T, 3, 3>(final_mode, what, sp, tb, gM, gK, dc, da, st);
+                     const void *gK, void *dc, void *const *da, hipStream_t st, int64_t max_tasks) {
+    if (sp.p == 2 && sp.d == 2) return adj_what<T, 2, 2>(final_mode, what, sp, tb, gM, gK, dc, da, st, max_tasks);
+    if (sp.p == 2 && sp.d == 3) return adj_what<T, 2, 3>(final_mode, what, sp, tb, gM, gK, dc, da, st, max_tasks);
+    if (sp.p == 3 && sp.d == 2) return adj_what<T, 3, 2>(final_mode, what, sp, tb, gM, gK, dc, da, st, max_tasks);
+    if (sp.p == 3 && sp.d == 3) return adj_what<T, 3, 3>(final_mode, what, sp, tb, gM, gK, dc, da, st, max_tasks);
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 hipError_t launch_forward(int dtype, int final_mode, int what, const DevSpace &sp, const DevTabs &tb,
-                          const void *c, const void *const *a, void *M, void *K, hipStream_t stream) {
-    if (dtype == 0) return fwd_shape<float>(final_mode, what, sp, tb, c, a, M, K, stream);
-    return fwd_shape<double>(final_mode, what, sp, tb, c, a, M, K, stream);
+                          const void *c, const void *const *a, void *M, void *K, hipStream_t stream,
+                          int64_t max_tasks) {
+    if (dtype == 0) return fwd_shape<float>(final_mode, what, sp, tb, c, a, M, K, stream, max_tasks);
+    return fwd_shape<double>(final_mode, what, sp, tb, c, a, M, K, stream, max_tasks);
 }
 
 hipError_t launch_apply(int dtype, int what, bool ones, const DevSpace &sp, const DevTabs &tb, const void *c,
-                        const void *const *a, const void *x, void *y, hipStream_t stream) {
-    if (dtype == 0) return apply_shape<float>(what, ones, sp, tb, c, a, x, y, stream);
-    return apply_shape<double>(what, ones, sp, tb, c, a, x, y, stream);
+                        const void *const *a, const void *x, void *y, hipStream_t stream, int64_t max_tasks) {
+    if (dtype == 0) return apply_shape<float>(what, ones, sp, tb, c, a, x, y, stream, max_tasks);
+    return apply_shape<double>(what, ones, sp, tb, c, a, x, y, stream, max_tasks);
 }
 
 hipError_t launch_adjoint(int dtype, int final_mode, int what, const DevSpace &sp, const DevTabs &tb,
-                          const void *gM, const void *gK, void *dc, void *const *da, hipStream_t stream) {
-    if (dtype == 0) return adj_shape<float>(final_mode, what, sp, tb, gM, gK, dc, da, stream);
-    return adj_shape<double>(final_mode, what, sp, tb, gM, gK, dc, da, stream);
+                          const void *gM, const void *gK, void *dc, void *const *da, hipStream_t stream,
+                          int64_t max_tasks) {
+    if (dtype == 0) return adj_shape<float>(final_mode, what, sp, tb, gM, gK, dc, da, stream, max_tasks);
+    return adj_shape<double>(final_mode, what, sp, tb, gM, gK, dc, da, stream, max_tasks);
 }
 
 }  // namespace wqa

@@ -164,3 +164,42 @@ def test_long_uniform_direction(wqa, p):
         T = sp.tables(kind, 0)
         far, near = n - 2 * p - 1, 2 * p
         assert np.abs(T[far] - T[near]).max() <= 64 * bound * np.abs(T[near]).max()
+
+
+def _reversed_interior(x, w, n, Q, p):
+    """The rule with the node order of every row at least p from both ends reversed (the
+    same exact rule, listed right to left)."""
+    xr, wr = x.reshape(n, Q).copy(), w.reshape(n, Q).copy()
+    xr[p:n - p] = xr[p:n - p, ::-1]
+    wr[p:n - p] = wr[p:n - p, ::-1]
+    return xr.reshape(-1), wr.reshape(-1)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_reordered_nodes_are_accepted_and_leave_the_band(wqa, p):
+    """Any order of a row's nodes is the same exact rule, so wqa_set_rules accepts it; the
+    table entries of node q are then nonzero outside q <= s <= q + p, the pattern the
+    kernels' banded loops rely on (the library must notice and take the full loops; the
+    GPU tests check the results)."""
+    n_el = (7, 9)
+    sp = wqa.Space(2, p, n_el, device=None)
+    Q, S, n = p + 1, 2 * p + 1, n_el[0] + p
+    for kind in (wqa.MASS, wqa.STIFFNESS):
+        x, w = sp.rules(kind, 0)
+        xr, wr = _reversed_interior(x.reshape(-1), w.reshape(-1), n, Q, p)
+        sp.set_rules(kind, 0, xr, wr)                     # validated: exact, inside the support
+        np.testing.assert_array_equal(sp.rules(kind, 0)[0].reshape(-1), xr)
+        T = sp.tables(kind, 0)
+        q, s = np.meshgrid(np.arange(Q), np.arange(S), indexing="ij")
+        outside = (s < q) | (s > q + p)
+        assert np.abs(T[p:n - p][:, outside]).max() > 1e-3
+
+
+def test_dispatch_limit_arguments(wqa):
+    sp = wqa.Space(2, 2, (4, 4), device=None)
+    sp.set_dispatch_limit(1)
+    sp.set_dispatch_limit(0)
+    sp.set_dispatch_limit(1 << 40)                        # clamped to the default
+    with pytest.raises(wqa.WQAError, match="EINVAL"):
+        sp.set_dispatch_limit(-1)
+    assert wqa.lib.wqa_set_dispatch_limit(None, 5) == -1
