@@ -61,3 +61,32 @@ def test_oracle_spectrum_converges_at_rate_2p(eig, p):
         errs.append((lam[9] - exact[9]) / exact[9])
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert abs(rates[-1] - 2 * p) < 0.35, (errs, rates)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_gram_1d_and_fast_diagonalization(eig, p):
+    # the preconditioner's 1D matrices are the exact Galerkin ones (scipy reference with
+    # another Gauss order), and the fast diagonalization inverts the Kronecker sum
+    import reference_1d as r1
+    n_el = (5, 4, 6)
+    Ms, Ks = [], []
+    for e in n_el:
+        Mk, Kk = eig.gram_1d(p, e)
+        np.testing.assert_allclose(Mk, r1.gram(p, e, m=p + 3), rtol=0, atol=1e-15)
+        np.testing.assert_allclose(Kk, r1.gram(p, e, deriv=True, m=p + 3), rtol=0, atol=1e-12 * e * e)
+        keep = np.arange(1, Mk.shape[0] - 1)
+        Ms.append(Mk[np.ix_(keep, keep)])
+        Ks.append(Kk[np.ix_(keep, keep)])
+    K = (np.kron(np.kron(Ks[0], Ms[1]), Ms[2]) + np.kron(np.kron(Ms[0], Ks[1]), Ms[2])
+         + np.kron(np.kron(Ms[0], Ms[1]), Ks[2]))
+    x = np.random.default_rng(3).standard_normal(K.shape[0])
+    np.testing.assert_allclose(eig.fast_diagonalization(Ms, Ks)(K @ x), x, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("p,n_el", [(2, (16, 16)), (3, (6, 6, 6)), (2, (5, 7, 6))])
+def test_conjugate_gradient_inner_solves_give_the_same_spectrum(eig, p, n_el):
+    M, K = _oracle_matrices(p, n_el)
+    n = [e + p for e in n_el]
+    direct = eig.solve_laplace(M, K, n, p, count=10, inner_solver="direct")
+    pcg = eig.solve_laplace(M, K, n, p, count=10, inner_solver="pcg")
+    np.testing.assert_allclose(pcg, direct, rtol=1e-12, atol=0)

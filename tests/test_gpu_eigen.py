@@ -30,8 +30,8 @@ def test_spectrum_equals_oracle_assembly(eig, p, n_el):
     assert np.max(np.abs(got - want) / want) < 1e-11
 
 
-@pytest.mark.parametrize("dim,p,meshes", [(2, 2, (16, 32, 64)), (2, 3, (16, 32, 64)), (3, 2, (8, 16)),
-                                          (3, 3, (8, 16))])
+@pytest.mark.parametrize("dim,p,meshes", [(2, 2, (16, 32, 64)), (2, 3, (16, 32, 64)), (3, 2, (8, 16, 32)),
+                                          (3, 3, (8, 16, 32))])
 def test_tenth_eigenvalue_converges_at_rate_2p(eig, dim, p, meshes):
     exact = eig.exact_laplace_eigenvalues(dim, 10)[9]
     errs = []
@@ -41,5 +41,6 @@ def test_tenth_eigenvalue_converges_at_rate_2p(eig, dim, p, meshes):
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     print(f"d={dim} p={p} meshes {meshes}: relative errors {['%.3e' % e for e in errs]}, rates {rates}")
     assert all(e > 0 for e in errs)
-    # 3D meshes this coarse are still slightly pre-asymptotic (rates 4.3 and 6.5 on the oracle)
-    assert abs(rates[-1] - 2 * p) < (0.3 if dim == 2 else 0.6), (errs, rates)
+    # the 3D 32^3 problems (33^3 and 35^3 unknowns) solve with conjugate-gradient inner
+    # solves (eigen.solve_laplace); the last rate is asymptotic in 2D and 3D alike
+    assert abs(rates[-1] - 2 * p) < 0.3, (errs, rates)
