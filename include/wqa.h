@@ -171,6 +171,17 @@ wqa_status wqa_query(const wqa_ctx *ctx, int64_t *n_rows, int64_t *slots_per_row
 /* Selects how FP32 calls accumulate the final directional pass (default WQA_FINAL_F64). */
 wqa_status wqa_set_final_mode(wqa_ctx *ctx, wqa_final mode);
 
+/* Sets the distance, in values, between consecutive grid lines of the last direction in
+ * every grid-shaped buffer the calls read or write (c, a_k, f, dc, da_k): such a buffer
+ * then holds N_1 x .. x N_{d-1} lines of `pitch` values, whose first N_d values are the
+ * grid (Grid above) and whose rest is never read or written.  0 restores the dense
+ * layout (pitch N_d, the default).  Otherwise pitch must be a multiple of 4 and at least
+ * N_d (WQA_EINVAL).  A pitch that is a multiple of 32 (FP32) or 16 (FP64) values starts
+ * every grid line on a 128-byte boundary of a 128-byte aligned buffer, so that the
+ * adjoint writes each line's gradient runs as whole cache lines.  wqa_set_space resets
+ * it; WQA_ESTATE before a space is set. */
+wqa_status wqa_set_grid_pitch(wqa_ctx *ctx, int64_t pitch);
+
 /* Caps the wave tasks (tiles of consecutive rows) one kernel dispatch takes: launches
  * with more are queued as several dispatches on the same stream, with identical
  * results.  0 restores the default, 2^24 tasks, which keeps every dispatch below HIP's

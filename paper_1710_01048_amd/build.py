@@ -1,4 +1,5 @@
-"""Builds libwqa.so (host C ABI + gfx950 HIP kernels) in-tree with hipcc.
+"""Builds libwqa.so (host C ABI + gfx950 HIP kernels) and libwqa_probes.so (memory-pattern
+probes for the benchmark) in-tree with hipcc.
 
     python paper_1710_01048_amd/build.py [-q]
 
@@ -18,6 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libwqa.so")
+PROBES = os.path.join(HERE, "libwqa_probes.so")
 ARCH = "gfx950"
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
@@ -51,6 +53,11 @@ def build(verbose=False):
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, k_obj, h_obj], verbose)
     os.replace(tmp, LIB)
+    # the memory-pattern probes (measurement only; the bench loads them)
+    tmp = PROBES + ".tmp%d" % os.getpid()
+    _run([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *HIP_FLAGS, *inc, "-shared",
+          os.path.join(CSRC, "wqa_probes.hip"), "-o", tmp], verbose)
+    os.replace(tmp, PROBES)
     return LIB
 
 

@@ -549,6 +549,7 @@ struct wqa_ctx {
     // the rows at least p from both ends have tables that vanish outside q <= s <= q + p
     bool banded[2][wqa::kMaxDim] = {};
     int64_t max_tasks = wqa::kMaxTasksPerDispatch;      // wave tasks per kernel dispatch
+    int64_t pitch = 0;                                  // grid line pitch (0: dense, N of the last direction)
     // device copies
     void *dev = nullptr;
     size_t dev_bytes = 0;
@@ -884,6 +885,7 @@ wqa_status wqa_set_space(wqa_ctx *c, int dim, int degree, const int64_t *n_elem)
     if (rows > ((int64_t)1 << 40)) return fail(WQA_EINVAL, "wqa_set_space: %lld rows", (long long)rows);
     c->dim = dim;
     c->p = degree;
+    c->pitch = 0;
     for (int k = 0; k < wqa::kMaxDim; ++k) {
         c->nel[k] = k < dim ? n_elem[k] : 0;
         c->n[k] = k < dim ? n_elem[k] + degree : 0;
@@ -1022,6 +1024,17 @@ wqa_status wqa_set_final_mode(wqa_ctx *c, wqa_final mode) {
     return ok();
 }
 
+wqa_status wqa_set_grid_pitch(wqa_ctx *c, int64_t pitch) {
+    if (!c) return fail(WQA_EINVAL, "wqa_set_grid_pitch: NULL context");
+    if (!c->have_space) return fail(WQA_ESTATE, "wqa_set_grid_pitch: call wqa_set_space first");
+    const int64_t Nd = c->N[c->dim - 1];
+    if (pitch != 0 && (pitch < Nd || pitch % 4 != 0))
+        return fail(WQA_EINVAL, "wqa_set_grid_pitch: pitch %lld (need 0, or a multiple of 4 of at least %lld)",
+                    (long long)pitch, (long long)Nd);
+    c->pitch = pitch;
+    return ok();
+}
+
 wqa_status wqa_set_dispatch_limit(wqa_ctx *c, int64_t max_tasks) {
     if (!c) return fail(WQA_EINVAL, "wqa_set_dispatch_limit: NULL context");
     if (max_tasks < 0) return fail(WQA_EINVAL, "wqa_set_dispatch_limit: %lld tasks", (long long)max_tasks);
@@ -1050,6 +1063,7 @@ wqa_status ready(wqa_ctx *c, const char *who, wqa_dtype dtype) {
 void fill(const wqa_ctx *c, wqa::DevSpace &sp, wqa::DevTabs &tb, wqa_dtype dtype) {
     sp.d = c->dim;
     sp.p = c->p;
+    sp.ld = c->pitch ? c->pitch : c->N[c->dim - 1];
     sp.band = 0;
     for (int k = 0; k < c->dim; ++k)
         if (c->banded[WQA_MASS][k] && c->banded[WQA_STIFFNESS][k]) sp.band |= 1 << k;

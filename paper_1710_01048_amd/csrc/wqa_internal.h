@@ -18,6 +18,7 @@ struct DevSpace {
                           // tables (both kinds) that vanish outside q <= s <= q + p
     int64_t n[kMaxDim];   // basis functions per direction
     int64_t N[kMaxDim];   // grid points per direction (n * (p + 1))
+    int64_t ld;           // values between consecutive grid lines of the last direction (>= N[d-1])
 };
 
 // Largest number of wave tasks one kernel dispatch takes by default; larger launches

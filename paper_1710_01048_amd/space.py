@@ -63,6 +63,7 @@ class Space:
         check(lib.wqa_query(self._ctx, ctypes.byref(rows), ctypes.byref(slots), ctypes.byref(pts), dims))
         self.n_rows, self.slots_per_row, self.points_per_row = rows.value, slots.value, pts.value
         self.grid_shape = tuple(dims[k] for k in range(self.dim))
+        self.buffer_shape = self.grid_shape           # grid buffers: lines padded to the pitch
         self.n_basis = tuple(e + self.degree for e in self.n_elem)
 
     def __del__(self):
@@ -111,6 +112,13 @@ class Space:
     def set_final_mode(self, mode):
         check(lib.wqa_set_final_mode(self._ctx, int(mode)))
 
+    def set_grid_pitch(self, pitch):
+        """Grid buffers (fields and gradients) hold lines of `pitch` values along the last
+        direction, the first N_d of them the grid (0: dense).  buffer_shape follows."""
+        check(lib.wqa_set_grid_pitch(self._ctx, int(pitch)))
+        last = self.grid_shape[-1] if pitch == 0 else int(pitch)
+        self.buffer_shape = self.grid_shape[:-1] + (last,)
+
     def set_dispatch_limit(self, max_tasks):
         """Wave tasks per kernel dispatch (0: the default); larger launches are split."""
         check(lib.wqa_set_dispatch_limit(self._ctx, int(max_tasks)))
@@ -121,8 +129,8 @@ class Space:
             raise ValueError(f"{name} must be a tensor on {self.device}")
         if t.dtype not in _DTYPES or (dtype is not None and t.dtype != dtype):
             raise ValueError(f"{name}: dtype {t.dtype} (need float32 or float64, all alike)")
-        if tuple(t.shape) != self.grid_shape and tuple(t.shape) != (int(np.prod(self.grid_shape)),):
-            raise ValueError(f"{name}: shape {tuple(t.shape)}, grid is {self.grid_shape}")
+        if tuple(t.shape) != self.buffer_shape and tuple(t.shape) != (int(np.prod(self.buffer_shape)),):
+            raise ValueError(f"{name}: shape {tuple(t.shape)}, grid buffers are {self.buffer_shape}")
         if not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
         if t.data_ptr() % 16:
@@ -191,11 +199,11 @@ class Space:
             if g is not None:
                 self._matrix(g, name, dtype)
         if gM is not None:
-            dc = torch.empty(self.grid_shape, dtype=dtype, device=self.device) if dc is None else self._field(dc, "dc", dtype)
+            dc = torch.empty(self.buffer_shape, dtype=dtype, device=self.device) if dc is None else self._field(dc, "dc", dtype)
         else:
             dc = None
         if gK is not None:
-            da = [torch.empty(self.grid_shape, dtype=dtype, device=self.device) for _ in range(self.dim)] \
+            da = [torch.empty(self.buffer_shape, dtype=dtype, device=self.device) for _ in range(self.dim)] \
                 if da is None else [self._field(x, f"da[{k}]", dtype) for k, x in enumerate(da)]
         else:
             da = None
@@ -258,6 +266,8 @@ class WQAssemble(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, space, c, *a):
+        if space.buffer_shape != space.grid_shape:
+            raise ValueError("WQAssemble needs dense grid buffers (grid pitch 0): padding would get no gradient")
         ctx.space = space
         ctx.shapes = (c.shape,) + tuple(x.shape for x in a)     # grid-shaped or flat
         c = c.contiguous()

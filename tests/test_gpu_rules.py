@@ -128,3 +128,49 @@ def test_rule_change_waits_for_queued_work(wqa):
     for o in outs:
         assert torch.equal(o, ref)
     assert torch.equal(after, 2 * ref)
+
+
+@pytest.mark.parametrize("case", [(3, 3, (5, 6, 13)), (2, 2, (5, 21)), (3, 2, (4, 3, 9))],
+                         ids=lambda c: "d%d-p%d" % c[:2])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_grid_pitch_gives_the_same_bits(wqa, case, dtype):
+    """Grid buffers whose last-direction lines are padded to a pitch: every call reads and
+    writes the same values at the same grid points as with dense buffers, and never
+    touches the padding (NaN there in the inputs stays out of the results, NaN there in
+    the gradient buffers stays NaN)."""
+    d, p, n_el = case
+    sp = wqa.Space(d, p, n_el)
+    fields = ph._random_fields(p, n_el, 91)
+    f = [torch.from_numpy(v).to(sp.device, dtype) for v in fields]
+    gM = si.upstream_gradient(n_el, p, 92, dtype, sp.device)
+    gK = si.upstream_gradient(n_el, p, 93, dtype, sp.device)
+    x = torch.randn(sp.n_rows, generator=torch.Generator().manual_seed(94)).to(sp.device, dtype)
+
+    def run(fs):
+        M, K = sp.assemble_fused(fs[0], fs[1:])
+        dc, da = sp.adjoint(gM, gK, torch.full(sp.buffer_shape, float("nan"), dtype=dtype, device=sp.device),
+                            [torch.full(sp.buffer_shape, float("nan"), dtype=dtype, device=sp.device)
+                             for _ in range(d)])
+        return [M, K, sp.apply_mass(fs[0], x), sp.apply_stiffness(fs[1:], x), sp.load_vector(fs[0])], [dc, *da]
+
+    dense, gdense = run(f)
+    Nd = sp.grid_shape[-1]
+    pitch = (Nd + 31) // 32 * 32 + 4
+    sp.set_grid_pitch(pitch)
+    assert sp.buffer_shape == sp.grid_shape[:-1] + (pitch,)
+    padded = []
+    for v in f:
+        buf = torch.full(sp.buffer_shape, float("nan"), dtype=dtype, device=sp.device)
+        buf[..., :Nd] = v
+        padded.append(buf)
+    mats, grads = run(padded)
+    torch.cuda.synchronize()
+    for a, b in zip(dense, mats):
+        assert torch.equal(a, b)
+    for a, b in zip(gdense, grads):
+        assert torch.equal(a, b[..., :Nd])
+        assert torch.isnan(b[..., Nd:]).all()
+    with pytest.raises(ValueError):
+        wqa.WQAssemble.apply(sp, *padded)
+    sp.set_grid_pitch(0)
+    assert sp.buffer_shape == sp.grid_shape

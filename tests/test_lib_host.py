@@ -203,3 +203,21 @@ def test_dispatch_limit_arguments(wqa):
     with pytest.raises(wqa.WQAError, match="EINVAL"):
         sp.set_dispatch_limit(-1)
     assert wqa.lib.wqa_set_dispatch_limit(None, 5) == -1
+
+
+def test_grid_pitch_arguments(wqa):
+    sp = wqa.Space(3, 3, (4, 5, 6), device=None)
+    Nd = sp.grid_shape[-1]                                # (6 + 3) * 4 = 36
+    sp.set_grid_pitch(64)
+    assert sp.buffer_shape == sp.grid_shape[:-1] + (64,)
+    for bad in (Nd - 4, 38, -4):                          # too short, not a multiple of 4, negative
+        with pytest.raises(wqa.WQAError, match="EINVAL"):
+            sp.set_grid_pitch(bad)
+    sp.set_grid_pitch(0)
+    assert sp.buffer_shape == sp.grid_shape
+    ctx = wqa.Space(2, 2, (4, 4), device=None, rules=None)
+    fresh = ctypes.c_void_p()
+    assert wqa.lib.wqa_create(ctypes.byref(fresh), -1) == 0
+    assert wqa.lib.wqa_set_grid_pitch(fresh, 64) == -2  # no space yet
+    wqa.lib.wqa_destroy(fresh)
+    del ctx
