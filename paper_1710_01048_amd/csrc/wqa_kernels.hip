@@ -423,7 +423,7 @@ __device__ __forceinline__ void forward_body(const DevSpace &sp, const DevTabs &
     using F = Forward<T, P, D, FINAL, BAND, R>;
     constexpr int Q = F::Q, S = F::S;
     using FT = typename F::FT;
-    F fw{sp, tb, t, stage, lane, lane - t.r * S, sp.N[1], (D == 3) ? sp.N[2] : 1};
+    F fw{sp, tb, t, stage, lane, lane - t.r * S, (D == 3) ? sp.N[1] : sp.ld, (D == 3) ? sp.ld : 1};
     const int64_t rs = (int64_t)Q * S;
     cptr<T> M2 = table<T>(tb, 0, 1) + (D == 3 ? t.i2 : 0) * rs;
     cptr<T> K2 = table<T>(tb, 1, 1) + (D == 3 ? t.i2 : 0) * rs;
@@ -576,12 +576,59 @@ __device__ __forceinline__ void lds_row(uint32_t a, T (&g)[S]) {
     g[S - 1] = x3;
 }
 
+// P+1 consecutive values of a ring slab at a per-lane address, read and waited for like
+// lds_row: the band s = q .. q+P of one slab row that a lane with node q meets when the
+// row's last-direction table is banded.
+template <typename T, int P>
+__device__ __forceinline__ void lds_band(uint32_t a, T (&g)[P + 1]) {
+    static_assert(P == 2 || P == 3, "p = 2 or 3");
+    using T2 = T __attribute__((ext_vector_type(2)));
+    T2 x0, x1;
+    T x2;
+    if constexpr (sizeof(T) == 4 && P == 3) {
+        asm volatile(
+            "ds_read2_b32 %0, %2 offset1:1\n\t"
+            "ds_read2_b32 %1, %2 offset0:2 offset1:3\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(x0), "=&v"(x1) : "v"(a) : "memory");
+        g[2] = x1.x;
+        g[3] = x1.y;
+    } else if constexpr (sizeof(T) == 4) {
+        asm volatile(
+            "ds_read2_b32 %0, %2 offset1:1\n\t"
+            "ds_read_b32 %1, %2 offset:8\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(x0), "=&v"(x2) : "v"(a) : "memory");
+        g[2] = x2;
+    } else if constexpr (P == 3) {
+        asm volatile(
+            "ds_read2_b64 %0, %2 offset1:1\n\t"
+            "ds_read2_b64 %1, %2 offset0:2 offset1:3\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(x0), "=&v"(x1) : "v"(a) : "memory");
+        g[2] = x1.x;
+        g[3] = x1.y;
+    } else {
+        asm volatile(
+            "ds_read2_b64 %0, %2 offset1:1\n\t"
+            "ds_read_b64 %1, %2 offset:16\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(x0), "=&v"(x2) : "v"(a) : "memory");
+        g[2] = x2;
+    }
+    g[0] = x0.x;
+    g[1] = x0.y;
+}
+
 template <typename T>
 __device__ __forceinline__ uint32_t lds_addr(const T *p) {
     return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) T *)p;
 }
 
-template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R, int RING>
+// LB: every row of the tile is at least P from both ends of its line and the last
+// direction's tables are banded, so a lane with node q_d only meets the slots
+// s_d = q_d .. q_d + P of each slab row (tl then holds those P+1 table entries).
+template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R, int RING, bool LB = false>
 struct Adjoint {
     static constexpr int Q = P + 1, S = 2 * P + 1;
     static constexpr int SL = (D == 3) ? S * S : S;     // slots of one s1 slab
@@ -595,6 +642,7 @@ struct Adjoint {
     static_assert(NPF <= 32, "one validity bit per load");
     static_assert(RING >= 2 && RING <= 4 && (RING - 1) * NPF < 64, "ring depth");
     static constexpr bool LIMIT = sizeof(T) == 8;
+    static constexpr int NT = LB ? P + 1 : S;            // last-direction table entries per lane
 
     const DevSpace &sp;
     const Tile &t;
@@ -684,14 +732,15 @@ struct Adjoint {
     // Z[zi][q2] (+)= sum_{s2} (sum_{s3} G[s1][s2][s3] tl[s3]) t2[q2][s2] for NSET sets that
     // share the slab (tl[m], t2[m]); d = 2: Z[zi][0] = sum_{s2} G[s1][s2] tl[s2].
     template <int NSET, int NZ>
-    __device__ __forceinline__ void slab_contract(const T *slab, int zi, const T (&tl)[NSET][S],
+    __device__ __forceinline__ void slab_contract(const T *slab, int zi, const T (&tl)[NSET][NT],
                                                   const cptr<T> (&t2)[NSET], T (&Z)[NSET][NZ][NQ2]) const {
-        const T *row = slab + (t.r < t.rows_here ? t.r : 0) * SL;
+        const T *row = slab + (t.r < t.rows_here ? t.r : 0) * SL + (LB ? ql : 0);
         if constexpr (D == 3) {
 #pragma unroll
             for (int s2 = 0; s2 < S; ++s2) {
-                T g[S];
-                lds_row<T, S>(lds_addr(row + s2 * S), g);
+                T g[NT];
+                if constexpr (LB) lds_band<T, P>(lds_addr(row + s2 * S), g);
+                else lds_row<T, S>(lds_addr(row + s2 * S), g);
                 // the table entries of one s2 at a time in scalar registers (a whole slab's
                 // would not fit beside everything else)
                 cptr<T> t2r[NSET];
@@ -701,7 +750,7 @@ struct Adjoint {
                 for (int m = 0; m < NSET; ++m) {
                     T y = T(0);
 #pragma unroll
-                    for (int s3 = 0; s3 < S; ++s3) y = fma(g[s3], tl[m][s3], y);
+                    for (int s3 = 0; s3 < NT; ++s3) y = fma(g[s3], tl[m][s3], y);
 #pragma unroll
                     for (int q2 = 0; q2 < Q; ++q2)
                         if (!BAND || in_band<P>(q2, s2)) Z[m][zi][q2] = fma(y, t2r[m][q2 * S + s2], Z[m][zi][q2]);
@@ -711,13 +760,14 @@ struct Adjoint {
                 if constexpr (LIMIT) __builtin_amdgcn_sched_barrier(0);
             }
         } else {
-            T g[S];
-            lds_row<T, S>(lds_addr(row), g);
+            T g[NT];
+            if constexpr (LB) lds_band<T, P>(lds_addr(row), g);
+            else lds_row<T, S>(lds_addr(row), g);
 #pragma unroll
             for (int m = 0; m < NSET; ++m) {
                 T y = T(0);
 #pragma unroll
-                for (int s2 = 0; s2 < S; ++s2) y = fma(g[s2], tl[m][s2], y);
+                for (int s2 = 0; s2 < NT; ++s2) y = fma(g[s2], tl[m][s2], y);
                 Z[m][zi][0] = y;
             }
         }
@@ -727,7 +777,7 @@ struct Adjoint {
     template <int NSET, int NZ>
     __device__ __forceinline__ void emit_q1(int q1, const cptr<FT> (&f1)[NSET], const T (&Z)[NSET][NZ][NQ2],
                                             T *const (&out)[NSET]) const {
-        const int64_t N2 = sp.N[1], N3 = (D == 3) ? sp.N[2] : 1;
+        const int64_t N2 = (D == 3) ? sp.N[1] : sp.ld, N3 = (D == 3) ? sp.ld : 1;
         const uint32_t lo = (uint32_t)(t.il * Q + ql);
 #pragma unroll
         for (int m = 0; m < NSET; ++m) {
@@ -751,7 +801,7 @@ struct Adjoint {
     // over s1, Q x Q per set; the FP32 compensated and FP64-accumulated passes keep the
     // S x Q slab results Z[s1][q2] and sum them at the end.
     template <int NSET>
-    __device__ __forceinline__ void run(int pos0, const T (&tl)[NSET][S], const cptr<T> (&t2)[NSET],
+    __device__ __forceinline__ void run(int pos0, const T (&tl)[NSET][NT], const cptr<T> (&t2)[NSET],
                                         const cptr<FT> (&f1)[NSET], T *const (&out)[NSET]) const {
         constexpr bool RUNNING = (FINAL == 0);
         constexpr int NZ = RUNNING ? 1 : S;
@@ -807,7 +857,7 @@ struct Adjoint {
         }
         if constexpr (BAND && !RUNNING) return;
         if (t.active) {
-            const int64_t N2 = sp.N[1], N3 = (D == 3) ? sp.N[2] : 1;
+            const int64_t N2 = (D == 3) ? sp.N[1] : sp.ld, N3 = (D == 3) ? sp.ld : 1;
             const uint32_t lo = (uint32_t)(t.il * Q + ql);
 #pragma unroll
             for (int m = 0; m < NSET; ++m) {
@@ -837,13 +887,13 @@ struct Adjoint {
     }
 };
 
-template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R, int RING>
+template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R, int RING, bool LB = false>
 __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &tb, const Tile &t, uint32_t *ring,
                                              int lane, const T *__restrict__ gM, const T *__restrict__ gK,
                                              T *__restrict__ dc, T *__restrict__ da0, T *__restrict__ da1,
                                              T *__restrict__ da2) {
-    using A = Adjoint<T, P, D, FINAL, BAND, WPB, R, RING>;
-    constexpr int Q = A::Q, S = A::S;
+    using A = Adjoint<T, P, D, FINAL, BAND, WPB, R, RING, LB>;
+    constexpr int Q = A::Q, S = A::S, NT = A::NT;
     using FT = typename A::FT;
     constexpr bool DO_M = (WHAT & kWhatM) != 0, DO_K = (WHAT & kWhatK) != 0;
     const int ql = lane - t.r * Q;
@@ -868,11 +918,12 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
     // wait at every slab).  The table rows are a few KB shared by every wave: an L2 hit.
     // The first RING - 1 slabs always exist: a row reaches at least p + 1 slabs of each
     // matrix (p + 1 >= 3 >= RING - 1).
-    T tlM[S], tlK[S];
+    // (banded rows: only the entries s = ql .. ql + P of the lane's node)
+    T tlM[NT], tlK[NT];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        tlM[s] = ML[s];
-        tlK[s] = KL[s];
+    for (int s = 0; s < NT; ++s) {
+        tlM[s] = ML[(LB ? ql : 0) + s];
+        tlK[s] = KL[(LB ? ql : 0) + s];
     }
     pin(tlM);
     pin(tlK);
@@ -880,9 +931,9 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
 #pragma unroll
     for (int pos = 0; pos < RING - 1; ++pos) adj.issue(pos);
     if constexpr (DO_M) {
-        T tl[1][S];
+        T tl[1][NT];
 #pragma unroll
-        for (int s = 0; s < S; ++s) tl[0][s] = tlM[s];
+        for (int s = 0; s < NT; ++s) tl[0][s] = tlM[s];
         const cptr<T> t2[1] = {M2};
         const cptr<FT> f1[1] = {fM1};
         T *const out[1] = {dc};
@@ -892,9 +943,9 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
     if constexpr (DO_K) {
         if constexpr (D == 3) {
             // term 1: (K, M, M), term 2: (M, K, M), term 3: (M, M, K) in directions (1, 2, 3)
-            T tl[3][S];
+            T tl[3][NT];
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
+            for (int s = 0; s < NT; ++s) {
                 tl[0][s] = tlM[s];
                 tl[1][s] = tlM[s];
                 tl[2][s] = tlK[s];
@@ -905,9 +956,9 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
             adj.template run<3>(adj.nM, tl, t2, f1, out);
         } else {
             // term 1: (K, M), term 2: (M, K) in directions (1, 2)
-            T tl[2][S];
+            T tl[2][NT];
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
+            for (int s = 0; s < NT; ++s) {
                 tl[0][s] = tlM[s];
                 tl[1][s] = tlK[s];
             }
@@ -936,8 +987,14 @@ __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
     const int64_t task = task0 + (int64_t)block_chunked() * WPB + wave;
     if (task >= n_tasks) return;
     const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, Q, lane, INTERIOR ? (int)kLinesInterior : line_set);
-    adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING>(sp, tb, t, ring[wave], lane, gM, gK, dc, da0, da1,
-                                                              da2);
+    // interior kernel: tiles whose rows are all banded in the last direction too take the
+    // short last-direction loops (each tile picks its code path)
+    if (INTERIOR && ((sp.band >> (D - 1)) & 1) && t.t0 >= P && t.t0 + t.rows_here + P <= t.nl)
+        adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING, INTERIOR>(sp, tb, t, ring[wave], lane, gM, gK, dc,
+                                                                           da0, da1, da2);
+    else
+        adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING, false>(sp, tb, t, ring[wave], lane, gM, gK, dc,
+                                                                        da0, da1, da2);
 }
 
 // --------------------------------------------------------------------------------------
@@ -951,9 +1008,12 @@ __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
 // same rules, tables and samples as the assembled matrices, which are never stored.
 // ONES replaces x by 1 everywhere: by the partition of unity the mass product then
 // gives the load vector b_i = integral f B_i with f as the coefficient.
-template <typename T, int P, int D, bool BAND, bool ONES>
+// LB as in Adjoint: the tile's rows are banded in the last direction, so a lane with node
+// q_d reads and weighs only the window values s_d = q_d .. q_d + P.
+template <typename T, int P, int D, bool BAND, bool ONES, bool LB = false>
 struct Apply {
     static constexpr int Q = P + 1, S = 2 * P + 1, R = 64 / Q;
+    static constexpr int NT = LB ? P + 1 : S;            // last-direction table entries per lane
     static constexpr int W = R + 2 * P;                  // window length along the last direction
     static constexpr int NQ2 = (D == 3) ? Q : 1;
     static constexpr int NS2 = (D == 3) ? S : 1;
@@ -970,7 +1030,7 @@ struct Apply {
     // contracted to that point.
     template <int NSET, int NL>
     __device__ __forceinline__ T terms(const T *const (&f)[NSET], const cptr<T> (&t1)[NSET],
-                                       const cptr<T> (&t2)[NSET], const T (&tl)[NL][S], const int (&ls)[NSET]) const {
+                                       const cptr<T> (&t2)[NSET], const T (&tl)[NL][NT], const int (&ls)[NSET]) const {
         T X[NSET][Q][NQ2];
 #pragma unroll
         for (int m = 0; m < NSET; ++m)
@@ -984,10 +1044,10 @@ struct Apply {
             tsum[l] = T(0);
             if constexpr (ONES) {
 #pragma unroll
-                for (int s3 = 0; s3 < S; ++s3) tsum[l] += tl[l][s3];
+                for (int s3 = 0; s3 < NT; ++s3) tsum[l] += tl[l][s3];
             }
         }
-        const T *row = win + (t.r < t.rows_here ? t.r : 0);
+        const T *row = win + (t.r < t.rows_here ? t.r : 0) + (LB ? ql : 0);
         // s1 stays a loop: unrolled, the compiler hoists the whole window's reads and holds
         // them in registers (the banded skip over q1 becomes a uniform branch)
 #pragma unroll 1
@@ -1006,14 +1066,14 @@ struct Apply {
 #pragma unroll
                     for (int l = 0; l < NL; ++l) y[l] = tsum[l];
                 } else {
-                    T g[S];
+                    T g[NT];
 #pragma unroll
-                    for (int s3 = 0; s3 < S; ++s3) g[s3] = row[(s1 * NS2 + s2) * W + s3];
+                    for (int s3 = 0; s3 < NT; ++s3) g[s3] = row[(s1 * NS2 + s2) * W + s3];
 #pragma unroll
                     for (int l = 0; l < NL; ++l) {
                         y[l] = T(0);
 #pragma unroll
-                        for (int s3 = 0; s3 < S; ++s3) y[l] = fma(g[s3], tl[l][s3], y[l]);
+                        for (int s3 = 0; s3 < NT; ++s3) y[l] = fma(g[s3], tl[l][s3], y[l]);
                     }
                 }
 #pragma unroll
@@ -1035,7 +1095,7 @@ struct Apply {
 #pragma unroll
                         for (int q2 = 0; q2 < NQ2; ++q2) X[m][q1][q2] = fma(Z[m][q2], t1[m][q1 * S + s1], X[m][q1][q2]);
         }
-        const int64_t N2 = sp.N[1], N3 = (D == 3) ? sp.N[2] : 1;
+        const int64_t N2 = (D == 3) ? sp.N[1] : sp.ld, N3 = (D == 3) ? sp.ld : 1;
         const uint32_t lo = (uint32_t)(t.il * Q + ql);
         T acc = T(0);
 #pragma unroll
@@ -1053,31 +1113,31 @@ struct Apply {
     }
 };
 
-template <typename T, int P, int D, int WHAT, bool ONES, bool BAND>
+template <typename T, int P, int D, int WHAT, bool ONES, bool BAND, bool LB = false>
 __device__ __forceinline__ T apply_body(const DevSpace &sp, const DevTabs &tb, const Tile &t, const T *win, int lane,
                                         const T *__restrict__ cf, const T *__restrict__ a0,
                                         const T *__restrict__ a1, const T *__restrict__ a2) {
-    using A = Apply<T, P, D, BAND, ONES>;
-    constexpr int Q = A::Q, S = A::S;
+    using A = Apply<T, P, D, BAND, ONES, LB>;
+    constexpr int Q = A::Q, S = A::S, NT = A::NT;
     const int ql = lane - t.r * Q;
     const A ap{sp, t, win, ql};
     const int64_t rs = (int64_t)Q * S;
     cptr<T> M1 = table<T>(tb, 0, 0) + t.i1 * rs, K1 = table<T>(tb, 1, 0) + t.i1 * rs;
     cptr<T> M2 = table<T>(tb, 0, 1) + (D == 3 ? t.i2 : 0) * rs, K2 = table<T>(tb, 1, 1) + (D == 3 ? t.i2 : 0) * rs;
-    const T *ML = (const T *)tb.t[0][D - 1] + t.il * rs + ql * S;
-    const T *KL = (const T *)tb.t[1][D - 1] + t.il * rs + ql * S;
+    const T *ML = (const T *)tb.t[0][D - 1] + t.il * rs + ql * S + (LB ? ql : 0);
+    const T *KL = (const T *)tb.t[1][D - 1] + t.il * rs + ql * S + (LB ? ql : 0);
     if constexpr (WHAT == kWhatM) {
-        T tl[1][S];
+        T tl[1][NT];
 #pragma unroll
-        for (int s = 0; s < S; ++s) tl[0][s] = ML[s];
+        for (int s = 0; s < NT; ++s) tl[0][s] = ML[s];
         const T *const f[1] = {cf};
         const cptr<T> t1[1] = {M1}, t2[1] = {M2};
         const int ls[1] = {0};
         return ap.template terms<1, 1>(f, t1, t2, tl, ls);
     } else {
-        T tl[2][S];      // mass and stiffness entries of the last direction
+        T tl[2][NT];     // mass and stiffness entries of the last direction
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
+        for (int s = 0; s < NT; ++s) {
             tl[0][s] = ML[s];
             tl[1][s] = KL[s];
         }
@@ -1124,10 +1184,13 @@ __global__ __launch_bounds__(64 * kApplyWaves, sizeof(T) == 4 ? 4 : 2) void appl
         wave_lds_sync();
     }
     T v;
-    if (tile_banded<D, P>(sp, t))
-        v = apply_body<T, P, D, WHAT, ONES, true>(sp, tb, t, win[wave], lane, cf, a0, a1, a2);
-    else
+    const bool last_banded = ((sp.band >> (D - 1)) & 1) && t.t0 >= P && t.t0 + t.rows_here + P <= t.nl;
+    if (tile_banded<D, P>(sp, t)) {
+        if (last_banded) v = apply_body<T, P, D, WHAT, ONES, true, true>(sp, tb, t, win[wave], lane, cf, a0, a1, a2);
+        else v = apply_body<T, P, D, WHAT, ONES, true, false>(sp, tb, t, win[wave], lane, cf, a0, a1, a2);
+    } else {
         v = apply_body<T, P, D, WHAT, ONES, false>(sp, tb, t, win[wave], lane, cf, a0, a1, a2);
+    }
     // the row's value is the sum over its Q lanes (lanes r Q .. r Q + Q - 1)
     const int base = t.r * Q;
     T sum = v;
