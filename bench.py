@@ -9,9 +9,14 @@ before timing; outputs are preallocated.
 
 value = slots processed per second over the step: 2 x rows x 343 assembled (M and K)
 plus 2 x rows x 343 upstream-gradient slots consumed by the adjoint.  Also reported:
-the forward under every FP32 final-pass mode, the same workload in FP64, an HBM probe
-with plain PyTorch kernels, and (cpu_baseline) the FP64 CPU oracle timed on a row
-sample, which also states the error of every GPU result on that sample.
+the forward under every FP32 final-pass mode, the same workload in FP64, the memory-
+pattern probes of libwqa_probes.so (the ceiling of each kernel's byte pattern) and
+plain streaming, and (cpu_baseline) the FP64 CPU oracle timed on a row sample, which
+also states the error of every GPU result on that sample.
+
+Grid buffers (coefficient samples and gradients) are allocated with their last-direction
+lines padded to a multiple of 32 values (wqa_set_grid_pitch), so that every line starts
+on a 128-byte boundary; the padding is never read or written.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -36,6 +41,7 @@ SEED_FAMILY = 5                # seeds of the 160^3 workload's Fourier fields an
 METRIC = "assembled nnz/s (3D C2 cubic M+K) FP32 vs FP64 at stated err; adjoint nnz/s"
 MODES = (("plain", 0), ("dot2", 1), ("f64_accumulate", 2))
 HEADLINE_MODE = 2              # final pass accumulated in FP64 (mixed precision; every other stage FP32)
+LINE_ALIGN = 32                # grid lines padded to a multiple of this many values
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_160cubed.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1710_01048_amd", "csrc", "wqa_kernels.hip")
 
@@ -54,6 +60,7 @@ def parse():
                     help="leave out the other workloads (matrix-free products, 96^3 forward): profiler runs")
     ap.add_argument("--cube96-only", action="store_true",
                     help="run only the 96^3 deformed-cube forward and print its figures (profiler runs)")
+    ap.add_argument("--no-probes", action="store_true", help="leave out the memory-pattern probes")
     ap.add_argument("--profile-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -67,12 +74,25 @@ def ev():
     return torch.cuda.Event(enable_timing=True)
 
 
+def padded_pitch(sp):
+    return (sp.grid_shape[-1] + LINE_ALIGN - 1) // LINE_ALIGN * LINE_ALIGN
+
+
+def padded(sp, dense):
+    """`dense` (grid-shaped) copied into a buffer of sp.buffer_shape (padding left as is)."""
+    buf = torch.empty(sp.buffer_shape, dtype=dense.dtype, device=dense.device)
+    buf[..., :sp.grid_shape[-1]] = dense
+    return buf
+
+
 def make_inputs(sp, dtype):
     dev = sp.device
     fields = []
     for field in ["c", 0, 1, 2]:
         fid = 0 if field == "c" else field + 1
-        fields.append(si.fourier_grid(sp.grid_axes(field), si.fourier_modes(SEED_FAMILY, fid, 3), dtype, dev).contiguous())
+        dense = si.fourier_grid(sp.grid_axes(field), si.fourier_modes(SEED_FAMILY, fid, 3), dtype, dev)
+        fields.append(padded(sp, dense))
+        del dense
     gM = si.upstream_gradient(NEL, P, 1000 * SEED_FAMILY + 1, dtype, dev)
     gK = si.upstream_gradient(NEL, P, 1000 * SEED_FAMILY + 2, dtype, dev)
     return fields, gM, gK
@@ -115,8 +135,9 @@ class Sample:
         idx = [self.rows // (n[1] * n[2]), (self.rows // n[2]) % n[1], self.rows % n[2]]
         qs = np.array(np.unravel_index(np.arange(Q ** 3), [Q] * 3))
         off = np.zeros((self.rows.size, Q ** 3), dtype=np.int64)
+        dims = list(sp.buffer_shape)            # the last direction's lines may be padded
         for k in range(3):
-            off = off * (n[k] * Q) + idx[k][:, None] * Q + qs[k][None, :]
+            off = off * dims[k] + idx[k][:, None] * Q + qs[k][None, :]
         self.ridx = torch.from_numpy(self.rows).to(sp.device)
         self.pidx = torch.from_numpy(off.reshape(-1)).to(sp.device)
 
@@ -146,8 +167,8 @@ def run_steps(sp, fields, gM, gK, steps, warmup):
     every kernel, wall clock around the whole loop with synchronizations on both sides."""
     M = torch.empty(sp.n_rows, sp.slots_per_row, dtype=fields[0].dtype, device=sp.device)
     K = torch.empty_like(M)
-    dc = torch.empty_like(fields[0])
-    da = [torch.empty_like(fields[0]) for _ in range(3)]
+    dc = torch.empty(sp.buffer_shape, dtype=fields[0].dtype, device=sp.device)
+    da = [torch.empty_like(dc) for _ in range(3)]
     for _ in range(warmup):
         sp.assemble_fused(fields[0], fields[1:], M, K)
         sp.adjoint(gM, gK, dc, da)
@@ -210,14 +231,19 @@ def matrix_free(sp, args):
 
 def deformed_cube_forward(wqa, dev, reps=20):
     """The 3D C2 cubic forward on 96^3 elements (970,299 rows) with the deformed-cube
-    coefficients (det J, det J / J_kk^2 folded into c and a_k): fused M+K, FP32 (default
-    final pass) and FP64, event-timed, with the fraction of the 8 TB/s HBM peak."""
+    coefficients (det J, det J / J_kk^2 folded into c and a_k): fused M+K, FP32 under every
+    final pass and FP64, event-timed, with the fraction of the 8 TB/s HBM peak."""
     sp = wqa.Space(3, P, (96, 96, 96), device=dev)
-    out = {"rows": sp.n_rows}
-    for dtype, tag, b in ((torch.float32, "fp32", 4), (torch.float64, "fp64", 8)):
-        f = [si.deformed_cube_grid(sp.grid_axes(field), field, dtype, dev).contiguous() for field in ["c", 0, 1, 2]]
+    sp.set_grid_pitch(padded_pitch(sp))
+    out = {"rows": sp.n_rows, "grid_pitch": sp.buffer_shape[-1]}
+    runs = [(torch.float32, f"fp32_{name}", mode) for name, mode in MODES] + [(torch.float64, "fp64", None)]
+    for dtype, tag, mode in runs:
+        b = 4 if dtype == torch.float32 else 8
+        f = [padded(sp, si.deformed_cube_grid(sp.grid_axes(field), field, dtype, dev)) for field in ["c", 0, 1, 2]]
         M = torch.empty(sp.n_rows, sp.slots_per_row, dtype=dtype, device=dev)
         K = torch.empty_like(M)
+        if mode is not None:
+            sp.set_final_mode(mode)
         for _ in range(3):
             sp.assemble_fused(f[0], f[1:], M, K)
         e0, e1 = ev(), ev()
@@ -232,6 +258,55 @@ def deformed_cube_forward(wqa, dev, reps=20):
                     "achieved_GB_s": nbytes / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del f, M, K
         torch.cuda.empty_cache()
+    for name, _ in MODES:
+        out[f"fp32_{name}"]["speedup_vs_fp64"] = out["fp64"]["forward_ms"] / out[f"fp32_{name}"]["forward_ms"]
+    sp.set_final_mode(HEADLINE_MODE)
+    return out
+
+
+def pattern_probes(sp, fields, M, K, gM, gK, grads, reps=10):
+    """Memory-pattern probes (libwqa_probes.so) on the step's own buffers: each moves the
+    bytes one kernel moves, in its tiles and work-group order, without arithmetic -- the
+    ceiling of that kernel's data layout on this GPU -- plus plain streaming at 2 GiB."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1710_01048_amd", "libwqa_probes.so"))
+    vp = ctypes.c_void_p
+    lib.wqap_stream.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int64, vp]
+    lib.wqap_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(vp), vp, vp, vp]
+    lib.wqap_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int64), vp, vp, ctypes.POINTER(vp), vp]
+    stream = lambda: vp(torch.cuda.current_stream().cuda_stream)
+    ne = (ctypes.c_int64 * 3)(*NEL)
+    pad = 256 if sp.buffer_shape[-1] == padded_pitch(sp) != sp.grid_shape[-1] else 0
+
+    def timed(fn):
+        rc = fn()
+        assert rc == 0, f"probe refused ({rc})"
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    fp = (vp * 4)(*[t.data_ptr() for t in fields])
+    gp = (vp * 4)(*[t.data_ptr() for t in grads])
+    out["forward_pattern_ms"] = timed(lambda: lib.wqap_forward(3 | pad, 0, P, ne, fp, vp(M.data_ptr()),
+                                                               vp(K.data_ptr()), stream()))
+    out["adjoint_pattern_ms"] = timed(lambda: lib.wqap_adjoint(3, pad, 0, P, ne, vp(gM.data_ptr()),
+                                                               vp(gK.data_ptr()), gp, stream()))
+    nb = 2 << 30
+    a = torch.empty(nb // 4, dtype=torch.float32, device=sp.device)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for name, what, moved in (("write", 0, nb), ("read", 1, nb), ("copy", 2, 2 * nb)):
+        ms = timed(lambda: lib.wqap_stream(what, vp(b.data_ptr()), vp(a.data_ptr()), nb, stream()))
+        out[f"stream_{name}_GBs"] = moved / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
     return out
 
 
@@ -239,8 +314,8 @@ def make_inputs_fields(sp, dtype):
     fields = []
     for field in ["c", 0, 1, 2]:
         fid = 0 if field == "c" else field + 1
-        fields.append(si.fourier_grid(sp.grid_axes(field), si.fourier_modes(SEED_FAMILY, fid, 3), dtype,
-                                      sp.device).contiguous())
+        fields.append(padded(sp, si.fourier_grid(sp.grid_axes(field), si.fourier_modes(SEED_FAMILY, fid, 3), dtype,
+                                                  sp.device)))
     return fields, None, None
 
 
@@ -319,9 +394,10 @@ def main():
         del src, dst
         log("calibration copy: 3 x 1 GiB read + 1 GiB written")
     sp = wqa.Space(3, P, NEL, device=dev)
+    sp.set_grid_pitch(padded_pitch(sp))
     nnz_mat = sp.n_rows * sp.slots_per_row
     nnz_step = 4 * nnz_mat
-    log(f"space: {sp.n_rows} rows x {sp.slots_per_row} slots, grid {sp.grid_shape}")
+    log(f"space: {sp.n_rows} rows x {sp.slots_per_row} slots, grid {sp.grid_shape}, buffers {sp.buffer_shape}")
 
     sample = None
     if not args.no_cpu_baseline:
@@ -355,6 +431,12 @@ def main():
     if sample is not None:
         mode_rows["headline"] = sample.matrices(r32["out"][0], r32["out"][1])
         g32 = (sample.upstream(gM, gK), sample.grads([r32["out"][2]] + list(r32["out"][3])))
+    patterns = None
+    if not args.no_probes:
+        M, K, dc, da = r32["out"]
+        patterns = pattern_probes(sp, fields, M, K, gM, gK, [dc] + list(da))
+        del M, K, dc, da
+        log(f"pattern probes: {patterns}")
     del r32["out"], fields, gM, gK
     torch.cuda.empty_cache()
 
@@ -391,17 +473,22 @@ def main():
                    "adjoint_fp32_mk": sp.n_rows * 4 * sp.points_per_row * 4}
     best_probe = max(probe.values())
 
-    def roof(ms, kernel):
+    def roof(ms, kernel, pattern_ms):
         achieved = alg_bytes / (ms * 1e-3) / 1e9
         traffic = traffic_for(kernel)
         wb = write_bytes[kernel]
-        return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": alg_bytes,
-                "write_bytes": wb, "write_frac": wb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                "frac_of_best_probe": achieved / best_probe}
+        out = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": alg_bytes,
+               "write_bytes": wb, "write_frac": wb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "frac_of_best_probe": achieved / best_probe}
+        if pattern_ms is not None:
+            # the same bytes in the same pattern without arithmetic (libwqa_probes.so)
+            out["pattern_ceiling"] = alg_bytes / (pattern_ms * 1e-3) / 1e9
+            out["frac_of_pattern_ceiling"] = pattern_ms / ms
+        return out
 
-    roof_fwd = roof(r32["fwd_ms"], "forward_fp32_mk")
-    roof_adj = roof(r32["adj_ms"], "adjoint_fp32_mk")
+    roof_fwd = roof(r32["fwd_ms"], "forward_fp32_mk", patterns and patterns["forward_pattern_ms"])
+    roof_adj = roof(r32["adj_ms"], "adjoint_fp32_mk", patterns and patterns["adjoint_pattern_ms"])
     line = {
         "metric": METRIC,
         "value": nnz_step / (step_ms * 1e-3),
@@ -420,7 +507,7 @@ def main():
                                "directional pass accumulated in FP64 (Dot2-compensated FP32 pass reported beside it)",
                    "final_pass": "f64_accumulate",
                    "rows": sp.n_rows, "slots_per_row": sp.slots_per_row, "nnz_per_step": nnz_step,
-                   "parallelism": "single GPU"},
+                   "grid_pitch": sp.buffer_shape[-1], "parallelism": "single GPU"},
         "forward_ms": r32["fwd_ms"],
         "adjoint_ms": r32["adj_ms"],
         "kernel_ms_per_call": r32["stats"],
@@ -430,6 +517,7 @@ def main():
         "roofline": roof_fwd if r32["fwd_ms"] >= r32["adj_ms"] else roof_adj,
         "roofline_by_kernel": {"forward": roof_fwd, "adjoint": roof_adj},
         "hbm_probe_torch": probe,
+        "pattern_probes": patterns,
         "matrix_free": mfree,
         "forward_96cubed_deformed_cube": cube96,
         "rule_counts": counts.report(P, NEL),
@@ -444,6 +532,16 @@ def main():
         line["fp32_vs_fp64_speedup"] = {"forward": r64["fwd_ms"] / r32["fwd_ms"],
                                         "adjoint": r64["adj_ms"] / r32["adj_ms"],
                                         "step": (r64["fwd_ms"] + r64["adj_ms"]) / (r32["fwd_ms"] + r32["adj_ms"])}
+    # every FP32 final pass of the forward: its time, its fraction of the HBM peak and its
+    # speedup over the FP64 forward (errors against the oracle in accuracy_vs_oracle)
+    line["final_pass_modes"] = {
+        name: {"forward_ms": ms, "frac_of_hbm_peak": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "speedup_vs_fp64_forward": (r64["fwd_ms"] / ms) if r64 is not None else None,
+               "arithmetic": {"plain": "FP32 fused multiply-adds",
+                              "dot2": "compensated summation in FP32 (Ogita-Rump-Oishi Dot2)",
+                              "f64_accumulate": "FP32 stage results times FP64 table entries, summed in FP64 "
+                                                "(mixed precision; the headline)"}[name]}
+        for name, ms in mode_ms.items()}
     if sample is not None:
         from oracle import assembly as oa
         up = g64[0] if g64 is not None else g32[0]

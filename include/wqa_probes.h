@@ -51,7 +51,12 @@ int wqap_fronts(void *dst, int k, int64_t spacing, int64_t per_front, void *hip_
  * slab.  Bits 6-7 choose the work-group order (0: each XCD a contiguous share, 1:
  * dispatch order, 2: runs of 8 tiles per XCD); bit 8 (layout 0 only) writes the outputs
  * with grid lines padded to a multiple of 32 values (outputs of N_1 N_2 pitch values, pitch
- * = N_3 rounded up to 32).  out[4] = dc, da_1, da_2, da_3. */
+ * = N_3 rounded up to 32); bit 9 (layout 0 only) stores the gradients row by row
+ * ([rows][(p+1)^3], each tile's rows of a field one contiguous block, written with 16-byte
+ * stores after each matrix's last slab); bit 10 (p = 3) the same layout written q_1 by q_1
+ * as each completes, one 16-byte store per lane (64 bytes per row); bit 11 the same layout
+ * after each matrix's last slab with one 4-byte store per lane and (q_1, q_2).  out[4] =
+ * dc, da_1, da_2, da_3. */
 int wqap_adjoint(int parts, int layout, int dtype, int p, const int64_t *n_elem, const void *gM,
                  const void *gK, void *const *out, void *hip_stream);
 
@@ -60,8 +65,11 @@ int wqap_adjoint(int parts, int layout, int dtype, int p, const int64_t *n_elem,
  * allow), and the tile's rows of M and K are written as two contiguous ranges with
  * 16-byte stores (nontemporal in FP32).  parts: bits 0-1 as above; bits 4-5 the
  * work-group order (0: the kernel's, runs of 8 consecutive tiles per XCD; 1: each XCD one
- * contiguous share; 2: dispatch order).  fields[4] = c, a_1, a_2, a_3; M is needed
- * even for the loads alone. */
+ * contiguous share; 2: dispatch order); bits 6-7: 1 ordinary stores in FP32, 2 M only;
+ * bit 8: fields with grid lines padded to a multiple of 32 values (as for the adjoint);
+ * bit 9: fields stored row by row ([rows][(p+1)^3]), each tile's samples of a field one
+ * contiguous block loaded with 16-byte loads.
+ * fields[4] = c, a_1, a_2, a_3; M is needed even for the loads alone. */
 int wqap_forward(int parts, int dtype, int p, const int64_t *n_elem, const void *const *fields, void *M,
                  void *K, void *hip_stream);
 

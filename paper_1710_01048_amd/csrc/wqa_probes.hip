@@ -17,6 +17,7 @@ struct Grid3 {
     int64_t n[3];   // basis functions per direction
     int64_t N[3];   // grid points per direction
     int64_t pitch;  // distance of consecutive grid lines of the outputs (N[2] unless padded)
+    int rowpts;     // samples stored row by row ([rows][(p+1)^3]) instead of on the grid
 };
 
 Grid3 grid_of(int p, const int64_t *n_elem) {
@@ -26,6 +27,7 @@ Grid3 grid_of(int p, const int64_t *n_elem) {
         g.N[k] = g.n[k] * (p + 1);
     }
     g.pitch = g.N[2];
+    g.rowpts = 0;
     return g;
 }
 
@@ -163,9 +165,44 @@ __global__ __launch_bounds__(64) void adjoint_tile_probe(Grid3 g, const T *__res
     const uint32_t lo = (uint32_t)(t0 * Q + lane);
     T acc = T(0);
     auto emit = [&](int run, int q1) {
-        if (!active) return;
         T *outs[3] = {run == 0 ? o0 : o1, o2, o3};
         const int nset = run == 0 ? 1 : 3;
+        if (g.rowpts == 3) {
+            // row by row, after each matrix's last slab, straight from the lanes: one
+            // 4-byte store per lane and (q1, q2), (p+1) values per row and store
+            if (q1 != Q - 1 || !active) return;
+            const int r = lane / Q, q3 = lane - r * Q;
+            for (int m = 0; m < nset; ++m)
+                for (int a1 = 0; a1 < Q; ++a1)
+#pragma unroll
+                    for (int q2 = 0; q2 < Q; ++q2)
+                        outs[m][(row0 + r) * Q * Q * Q + (a1 * Q + q2) * Q + q3] = acc + T(q2);
+            return;
+        }
+        if (g.rowpts == 2) {
+            // row by row, each q1 as it completes: the 4 lanes of a row hold its (p+1)^2
+            // values of that q1 (after a transpose within the quad), one 16-byte store each
+            // (p = 3: 64 bytes per row, 256 bytes apart)
+            if (!active) return;
+            using V4 = T __attribute__((ext_vector_type(4)));
+            const int r = lane / Q, j = lane - r * Q;
+            for (int m = 0; m < nset; ++m)
+                *reinterpret_cast<V4 *>(outs[m] + (row0 + r) * Q * Q * Q + q1 * Q * Q + j * Q) = V4{acc, acc, acc, acc};
+            return;
+        }
+        if (g.rowpts) {
+            // the tile's rows of each field are one contiguous block of rows_here (p+1)^3
+            // values: written with 16-byte stores once per matrix run
+            if (q1 != Q - 1) return;
+            using V4 = T __attribute__((ext_vector_type(4)));
+            const int nvec = rows_here * Q * Q * Q / 4;
+            for (int m = 0; m < nset; ++m) {
+                V4 *dst = reinterpret_cast<V4 *>(outs[m] + row0 * Q * Q * Q);
+                for (int k = lane; k < nvec; k += 64) dst[k] = V4{acc, acc, acc, acc};
+            }
+            return;
+        }
+        if (!active) return;
         for (int m = 0; m < nset; ++m)
 #pragma unroll
             for (int q2 = 0; q2 < Q; ++q2)
@@ -437,8 +474,11 @@ int adjoint_parts(int parts, int layout, const Grid3 &g, const void *gM, const v
     const int order = (layout >> 6) & 3;    // 0: each XCD a contiguous share, 1: dispatch, 2: runs of 8
     Grid3 gp = g;
     if (layout & 256) gp.pitch = (g.N[2] + 31) / 32 * 32;   // output lines start 128-byte aligned (FP32)
+    if (layout & 512) gp.rowpts = 1;                         // gradients stored row by row
+    if (layout & 1024) gp.rowpts = 2;                        // ... each q1 as it completes (p = 3)
+    if (layout & 2048) gp.rowpts = 3;                        // ... after the run, 4-byte stores
     layout &= 63;
-    if (layout == 0 && gp.pitch != g.N[2]) {
+    if (layout == 0 && (gp.pitch != g.N[2] || gp.rowpts)) {
         switch (parts) {
             case 2: return launch_adjoint_tile<T, P, 2>(gp, gM, gK, out, st, order);
             case 3: return launch_adjoint_tile<T, P, 3>(gp, gM, gK, out, st, order);
@@ -501,8 +541,32 @@ __global__ __launch_bounds__(64) void forward_probe(Grid3 g, const T *__restrict
     const int64_t t0 = (int64_t)tile * R;
     const int rows_here = (int)std::min<int64_t>(R, g.n[2] - t0);
     const int64_t row0 = line * g.n[2] + t0;
-    if constexpr (PARTS & 1) {
-        const int64_t N1 = g.N[1], N2 = g.N[2];
+    if ((PARTS & 1) && g.rowpts) {
+        // the tile's rows of each field: one contiguous block of rows_here (p+1)^3 samples
+        using V4 = T __attribute__((ext_vector_type(4)));
+        constexpr int QD = Q * Q * Q, NV = (R * QD / 4 + 63) / 64;
+        const int nvec = rows_here * QD / 4;
+        const T *fl[NF] = {f0, f1, f2, f3};
+        V4 v[NF][NV];
+#pragma unroll
+        for (int m = 0; m < NF; ++m)
+#pragma unroll
+            for (int it = 0; it < NV; ++it) {
+                const int k = lane + 64 * it;
+                v[m][it] = reinterpret_cast<const V4 *>(fl[m] + row0 * QD)[k < nvec ? k : 0];
+            }
+        T s = T(0);
+#pragma unroll
+        for (int m = 0; m < NF; ++m)
+#pragma unroll
+            for (int it = 0; it < NV; ++it) s += v[m][it][0];
+        if constexpr (!(PARTS & 2)) {
+            if (s == T(-12345)) Mo[lane] = s;          // keeps the loads (never true)
+        }
+        stage[lane] = s;
+        __builtin_amdgcn_wave_barrier();
+    } else if constexpr (PARTS & 1) {
+        const int64_t N1 = g.N[1], N2 = g.pitch;          // grid lines of the fields may be padded
         const int64_t base = ((i1 * Q) * N1 + i2 * Q) * N2 + t0 * Q;
         const T *fl[NF] = {f0, f1, f2, f3};
         int64_t off[IT];
@@ -623,7 +687,7 @@ int wqap_fronts(void *dst, int k, int64_t spacing, int64_t per_front, void *stre
 int wqap_adjoint(int parts, int layout, int dtype, int p, const int64_t *n_elem, const void *gM, const void *gK,
                  void *const *out, void *stream) {
     if (!geometry_ok(dtype, p, n_elem) || layout < 0 || (layout & 63) > 49 || ((layout >> 6) & 3) > 2 ||
-        layout >= 512 || !out)
+        layout >= 4096 || !out)
         return -1;
     if (((parts & 1) && (!gM || !gK)) || ((parts & 2) && (!out[0] || !out[1] || !out[2] || !out[3]))) return -1;
     const Grid3 g = grid_of(p, n_elem);
@@ -640,7 +704,10 @@ int wqap_forward(int parts, int dtype, int p, const int64_t *n_elem, const void 
     if (((parts & 1) && (!fields[0] || !fields[1] || !fields[2] || !fields[3])) || ((parts & 2) && (!M || !K)) ||
         !M)
         return -1;
-    const Grid3 g = grid_of(p, n_elem);
+    Grid3 g = grid_of(p, n_elem);
+    if (parts & 256) g.pitch = (g.N[2] + 31) / 32 * 32;      // fields with padded grid lines
+    if (parts & 512) g.rowpts = 1;                           // fields stored row by row
+    parts &= 255;
     hipStream_t st = (hipStream_t)stream;
     if (dtype == 0) return p == 2 ? forward_parts<float, 2>(parts, g, fields, M, K, st)
                                   : forward_parts<float, 3>(parts, g, fields, M, K, st);
