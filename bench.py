@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--cube96-only", action="store_true",
                     help="run only the 96^3 deformed-cube forward and print its figures (profiler runs)")
     ap.add_argument("--no-probes", action="store_true", help="leave out the memory-pattern probes")
+    ap.add_argument("--probe-sweep", type=int, default=0, metavar="N_EL",
+                    help="only time the memory-pattern probe variants on the N_EL^3 cubic space (the layout "
+                         "experiments behind the kernels' design) and print them")
     ap.add_argument("--profile-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -310,6 +313,93 @@ def pattern_probes(sp, fields, M, K, gM, gK, grads, reps=10):
     return out
 
 
+def probe_sweep(wqa, dev, n_el, reps=10):
+    """Every variant of the memory-pattern probes on the n_el^3 cubic space, FP32: the
+    forward's pattern (loads, stores, both) in three work-group orders, with ordinary or
+    nontemporal stores, padded lines or row-by-row samples; the adjoint's pattern in its
+    tile layout under three orders, with padded lines, row-by-row gradients (one block per
+    matrix, or q_1 by q_1, or 4-byte stores), line-wide work-groups, whole-tile loads and
+    stores after each matrix; streaming and k concurrent write fronts.  Milliseconds per
+    call and fractions of 8 TB/s for the whole pattern."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1710_01048_amd", "libwqa_probes.so"))
+    vp = ctypes.c_void_p
+    lib.wqap_stream.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int64, vp]
+    lib.wqap_fronts.argtypes = [vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, vp]
+    lib.wqap_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(vp), vp, vp, vp]
+    lib.wqap_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int64), vp, vp, ctypes.POINTER(vp), vp]
+    stream = lambda: vp(torch.cuda.current_stream().cuda_stream)
+
+    def timed(fn):
+        rc = fn()
+        if rc != 0:
+            return None
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return round(e0.elapsed_time(e1) / reps, 4)
+
+    sp = wqa.Space(3, P, (n_el,) * 3, device=dev, rules=None)
+    ne = (ctypes.c_int64 * 3)(n_el, n_el, n_el)
+    N = sp.grid_shape
+    cells = N[0] * N[1] * ((N[2] + LINE_ALIGN - 1) // LINE_ALIGN * LINE_ALIGN)
+    alg = sp.n_rows * (2 * sp.slots_per_row + 4 * sp.points_per_row) * 4
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    M = torch.randn(sp.n_rows, sp.slots_per_row, device=dev, generator=g)
+    K = torch.randn(sp.n_rows, sp.slots_per_row, device=dev, generator=g)
+    f = [torch.rand(cells, device=dev, generator=g) + 0.5 for _ in range(4)]
+    d = [torch.empty(cells, device=dev) for _ in range(4)]
+    fp = (vp * 4)(*[t.data_ptr() for t in f])
+    dp = (vp * 4)(*[t.data_ptr() for t in d])
+    out = {"space": f"{n_el}^3 cubic", "algorithmic_GB": alg / 1e9}
+    fwd = {}
+    for oname, order in (("xcd_runs_of_8", 0), ("xcd_shares", 1), ("dispatch", 2)):
+        for parts, pname in ((1, "loads"), (2, "stores"), (3, "both")):
+            fwd[f"{oname}/{pname}"] = timed(lambda: lib.wqap_forward(parts | (order << 4), 0, P, ne, fp, vp(M.data_ptr()),
+                                                                     vp(K.data_ptr()), stream()))
+    for name, code in (("ordinary_stores/stores", 2 | 64), ("ordinary_stores/both", 3 | 64),
+                       ("M_only/stores", 2 | 128), ("padded_lines/both", 3 | 256), ("row_samples/loads", 1 | 512),
+                       ("row_samples/both", 3 | 512)):
+        fwd[name] = timed(lambda: lib.wqap_forward(code, 0, P, ne, fp, vp(M.data_ptr()), vp(K.data_ptr()), stream()))
+    out["forward_ms"] = fwd
+    adj = {}
+    for name, layout, parts_list in (("tiles", 0, (1, 2, 3)), ("tiles_dispatch_order", 64, (2, 3)),
+                                     ("tiles_xcd_runs_of_8", 128, (2, 3)), ("tiles_padded_lines", 256, (2, 3)),
+                                     ("tiles_padded_lines_xcd_runs_of_8", 256 | 128, (2, 3)),
+                                     ("row_gradients_block", 512, (2, 3)), ("row_gradients_per_q1", 1024, (2, 3)),
+                                     ("row_gradients_4byte", 2048, (2, 3)), ("stores_after_each_matrix", 49, (2, 3)),
+                                     ("line_workgroups", 16 + 15, (2, 3)), ("whole_tile_loads", 48, (1, 2, 3))):
+        for parts in parts_list:
+            pname = {1: "loads", 2: "stores", 3: "both"}[parts]
+            adj[f"{name}/{pname}"] = timed(lambda: lib.wqap_adjoint(parts, layout, 0, P, ne, vp(M.data_ptr()),
+                                                                    vp(K.data_ptr()), dp, stream()))
+    out["adjoint_ms"] = adj
+    out["frac_of_hbm_peak"] = {k: {n: (alg / (v * 1e-3) / 1e9 / HBM_PEAK_GBS if v and n.endswith("both") else None)
+                                   for n, v in out[k].items()} for k in ("forward_ms", "adjoint_ms")}
+    del M, K, f, d
+    torch.cuda.empty_cache()
+    nb = 2 << 30
+    a = torch.empty(nb // 4, device=dev)
+    b = torch.empty(nb // 4 + (64 << 20), device=dev)
+    a.fill_(1.0)
+    st = {}
+    for name, what, moved in (("write", 0, nb), ("read", 1, nb), ("copy", 2, 2 * nb)):
+        ms = timed(lambda: lib.wqap_stream(what, vp(b.data_ptr()), vp(a.data_ptr()), nb, stream()))
+        st[f"{name}_TBs"] = moved / (ms * 1e-3) / 1e12 if ms else None
+    for k in (1, 16, 128):
+        per = (nb // k) // 4096 * 4096
+        ms = timed(lambda: lib.wqap_fronts(vp(b.data_ptr()), k, per, per, stream()))
+        st[f"fronts_{k}_write_TBs"] = per * k / (ms * 1e-3) / 1e12 if ms else None
+    out["stream"] = st
+    return out
+
+
 def make_inputs_fields(sp, dtype):
     fields = []
     for field in ["c", 0, 1, 2]:
@@ -384,6 +474,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.cube96_only:
         print(json.dumps({"forward_96cubed_deformed_cube": deformed_cube_forward(wqa, dev)}), flush=True)
+        return
+    if args.probe_sweep:
+        print(json.dumps({"probe_sweep": probe_sweep(wqa, dev, args.probe_sweep)}), flush=True)
         return
     if args.profile_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
