@@ -55,8 +55,9 @@ int wqap_fronts(void *dst, int k, int64_t spacing, int64_t per_front, void *hip_
  * ([rows][(p+1)^3], each tile's rows of a field one contiguous block, written with 16-byte
  * stores after each matrix's last slab); bit 10 (p = 3) the same layout written q_1 by q_1
  * as each completes, one 16-byte store per lane (64 bytes per row); bit 11 the same layout
- * after each matrix's last slab with one 4-byte store per lane and (q_1, q_2).  out[4] =
- * dc, da_1, da_2, da_3. */
+ * after each matrix's last slab with one 4-byte store per lane and (q_1, q_2); bit 12 (layout
+ * 0 only) a ring of 3 slabs, whose smaller LDS share lets 16 waves share a CU.  out[4] = dc,
+ * da_1, da_2, da_3. */
 int wqap_adjoint(int parts, int layout, int dtype, int p, const int64_t *n_elem, const void *gM,
                  const void *gK, void *const *out, void *hip_stream);
 

@@ -113,7 +113,7 @@ __device__ __forceinline__ void wait_vm() {
     asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-template <typename T, int P>
+template <typename T, int P, int RING_ = 0>
 struct AdjShape {
     static constexpr int Q = P + 1, S = 2 * P + 1, SL = S * S, SD = S * SL;
     static constexpr int R = 64 / Q;                    // rows per wave tile
@@ -121,15 +121,15 @@ struct AdjShape {
     static constexpr int NE = R * SL * U;               // dwords of one slab
     static constexpr int NPF = (NE + 63) / 64;          // loads per lane per slab
     static constexpr int SLOT = 64 * NPF;
-    static constexpr int RING = sizeof(T) == 4 ? 4 : 3;
+    static constexpr int RING = RING_ ? RING_ : (sizeof(T) == 4 ? 4 : 3);
 };
 
-template <typename T, int P, int PARTS, bool DEFER = false>
+template <typename T, int P, int PARTS, bool DEFER = false, int RING_ = 0>
 __global__ __launch_bounds__(64) void adjoint_tile_probe(Grid3 g, const T *__restrict__ gM, const T *__restrict__ gK,
                                                          T *__restrict__ o0, T *__restrict__ o1, T *__restrict__ o2,
                                                          T *__restrict__ o3, int64_t n_tasks, int tiles_per_line,
                                                          int order) {
-    using A = AdjShape<T, P>;
+    using A = AdjShape<T, P, RING_>;
     constexpr int Q = A::Q, S = A::S, SL = A::SL, SD = A::SD, R = A::R, U = A::U, NE = A::NE, NPF = A::NPF;
     constexpr int SLOT = A::SLOT, RING = A::RING;
     __shared__ __align__(16) uint32_t ring[RING * SLOT];
@@ -442,14 +442,14 @@ int launch_adjoint_bulk(const Grid3 &g, const void *gM, const void *gK, void *co
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
-template <typename T, int P, int PARTS, bool DEFER = false>
+template <typename T, int P, int PARTS, bool DEFER = false, int RING_ = 0>
 int launch_adjoint_tile(const Grid3 &g, const void *gM, const void *gK, void *const *out, hipStream_t st,
                         int order) {
     constexpr int R = AdjShape<T, P>::R;
     const int tiles = (int)((g.n[2] + R - 1) / R);
     const int64_t tasks = g.n[0] * g.n[1] * tiles;
     if (tasks >= (int64_t(1) << 31) / 64) return -1;
-    hipLaunchKernelGGL((adjoint_tile_probe<T, P, PARTS, DEFER>), dim3((unsigned)tasks), dim3(64), 0, st, g,
+    hipLaunchKernelGGL((adjoint_tile_probe<T, P, PARTS, DEFER, RING_>), dim3((unsigned)tasks), dim3(64), 0, st, g,
                        (const T *)gM, (const T *)gK, (T *)out[0], (T *)out[1], (T *)out[2], (T *)out[3], tasks,
                        tiles, order);
     return hipGetLastError() == hipSuccess ? 0 : -5;
@@ -477,8 +477,16 @@ int adjoint_parts(int parts, int layout, const Grid3 &g, const void *gM, const v
     if (layout & 512) gp.rowpts = 1;                         // gradients stored row by row
     if (layout & 1024) gp.rowpts = 2;                        // ... each q1 as it completes (p = 3)
     if (layout & 2048) gp.rowpts = 3;                        // ... after the run, 4-byte stores
+    const bool ring3 = (layout & 4096) != 0;                 // a ring of 3 slabs (more waves per CU)
     layout &= 63;
-    if (layout == 0 && (gp.pitch != g.N[2] || gp.rowpts)) {
+    if (layout == 0 && (ring3 || gp.pitch != g.N[2] || gp.rowpts)) {
+        if (ring3) {
+            switch (parts) {
+                case 2: return launch_adjoint_tile<T, P, 2, false, 3>(gp, gM, gK, out, st, order);
+                case 3: return launch_adjoint_tile<T, P, 3, false, 3>(gp, gM, gK, out, st, order);
+                default: return -1;
+            }
+        }
         switch (parts) {
             case 2: return launch_adjoint_tile<T, P, 2>(gp, gM, gK, out, st, order);
             case 3: return launch_adjoint_tile<T, P, 3>(gp, gM, gK, out, st, order);
@@ -687,7 +695,7 @@ int wqap_fronts(void *dst, int k, int64_t spacing, int64_t per_front, void *stre
 int wqap_adjoint(int parts, int layout, int dtype, int p, const int64_t *n_elem, const void *gM, const void *gK,
                  void *const *out, void *stream) {
     if (!geometry_ok(dtype, p, n_elem) || layout < 0 || (layout & 63) > 49 || ((layout >> 6) & 3) > 2 ||
-        layout >= 4096 || !out)
+        layout >= 8192 || !out)
         return -1;
     if (((parts & 1) && (!gM || !gK)) || ((parts & 2) && (!out[0] || !out[1] || !out[2] || !out[3]))) return -1;
     const Grid3 g = grid_of(p, n_elem);
