@@ -318,8 +318,10 @@ def probe_sweep(wqa, dev, n_el, reps=10):
     forward's pattern (loads, stores, both) in three work-group orders, with ordinary or
     nontemporal stores, padded lines or row-by-row samples; the adjoint's pattern in its
     tile layout under three orders, with padded lines, row-by-row gradients (one block per
-    matrix, or q_1 by q_1, or 4-byte stores), line-wide work-groups, whole-tile loads and
-    stores after each matrix; streaming and k concurrent write fronts.  Milliseconds per
+    matrix, or q_1 by q_1, or 4-byte stores, or blocks in the lanes' order), line-q_1
+    blocks, line-wide
+    work-groups, whole-tile loads, stores after each matrix, a ring of 3 slabs and at most 8
+    waves per CU; streaming and k concurrent write fronts.  Milliseconds per
     call and fractions of 8 TB/s for the whole pattern."""
     import ctypes
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1710_01048_amd", "libwqa_probes.so"))
@@ -374,7 +376,18 @@ def probe_sweep(wqa, dev, n_el, reps=10):
                                      ("tiles_padded_lines_xcd_runs_of_8", 256 | 128, (2, 3)),
                                      ("row_gradients_block", 512, (2, 3)), ("row_gradients_per_q1", 1024, (2, 3)),
                                      ("row_gradients_4byte", 2048, (2, 3)), ("stores_after_each_matrix", 49, (2, 3)),
-                                     ("line_workgroups", 16 + 15, (2, 3)), ("whole_tile_loads", 48, (1, 2, 3))):
+                                     ("line_workgroups", 16 + 15, (2, 3)), ("whole_tile_loads", 48, (1, 2, 3)),
+                                     ("tiles_padded_lines_xcd_runs_of_8_ring3", 256 | 128 | 4096, (3,)),
+                                     ("tiles_padded_lines_xcd_runs_of_8_8_waves_per_cu", 256 | 128 | 8192, (3,)),
+                                     ("row_gradients_block_xcd_runs_of_8", 512 | 128, (2, 3)),
+                                     ("row_gradients_block_8_waves_per_cu", 512 | 8192, (3,)),
+                                     ("row_gradients_block_xcd_runs_of_8_8_waves_per_cu", 512 | 128 | 8192, (3,)),
+                                     ("row_gradients_lane_order", 16384, (2, 3)),
+                                     ("row_gradients_lane_order_xcd_runs_of_8", 16384 | 128, (2, 3)),
+                                     ("row_gradients_lane_order_xcd_runs_of_8_8_waves_per_cu", 16384 | 128 | 8192,
+                                      (3,)),
+                                     ("line_q1_blocks", 32768, (2, 3)),
+                                     ("line_q1_blocks_xcd_runs_of_8", 32768 | 128, (2, 3))):
         for parts in parts_list:
             pname = {1: "loads", 2: "stores", 3: "both"}[parts]
             adj[f"{name}/{pname}"] = timed(lambda: lib.wqap_adjoint(parts, layout, 0, P, ne, vp(M.data_ptr()),

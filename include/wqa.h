@@ -182,6 +182,27 @@ wqa_status wqa_set_final_mode(wqa_ctx *ctx, wqa_final mode);
  * it; WQA_ESTATE before a space is set. */
 wqa_status wqa_set_grid_pitch(wqa_ctx *ctx, int64_t pitch);
 
+/* Layouts of the sample buffers (c, a_k, f, dc, da_k). */
+typedef enum wqa_samples {
+    WQA_SAMPLES_GRID = 0,  /* [N_1..N_d], Grid above (the default) */
+    WQA_SAMPLES_ROWS = 1   /* [rows][Q^d]: the Q^d points that row i owns, (i_k Q + q_k)_k,
+                              as one block at offset i Q^d (row order as for the matrices),
+                              point (q_1..q_d) at ((q_1 Q) + q_2) Q + q_3 (d = 3) or
+                              q_1 Q + q_2 (d = 2) within it */
+} wqa_samples;
+
+/* Selects the layout of every sample buffer the calls read or write (c, a_k, f, dc,
+ * da_k).  Both layouts hold the same values: each grid point belongs to exactly one row,
+ * the row whose rule it is a node of (Sec. 3), and WQA_SAMPLES_ROWS stores the Q^d samples
+ * of each row together, rows in order.  Every result is the same, bit for bit, in both
+ * layouts.  In the row layout a tile of consecutive rows reads (assembly, products) and
+ * writes (adjoint) its samples of a field as one contiguous block, which the adjoint
+ * writes with whole-block 16-byte stores.  wqa_set_space resets it to WQA_SAMPLES_GRID.
+ * WQA_EINVAL for other values; WQA_ESTATE before a space is set, or for WQA_SAMPLES_ROWS
+ * while a grid pitch is set (the pitch belongs to the grid layout; wqa_set_grid_pitch
+ * likewise refuses a nonzero pitch in the row layout). */
+wqa_status wqa_set_sample_layout(wqa_ctx *ctx, int layout);
+
 /* Caps the wave tasks (tiles of consecutive rows) one kernel dispatch takes: launches
  * with more are queued as several dispatches on the same stream, with identical
  * results.  0 restores the default, 2^24 tasks, which keeps every dispatch below HIP's

@@ -56,8 +56,13 @@ int wqap_fronts(void *dst, int k, int64_t spacing, int64_t per_front, void *hip_
  * stores after each matrix's last slab); bit 10 (p = 3) the same layout written q_1 by q_1
  * as each completes, one 16-byte store per lane (64 bytes per row); bit 11 the same layout
  * after each matrix's last slab with one 4-byte store per lane and (q_1, q_2); bit 12 (layout
- * 0 only) a ring of 3 slabs, whose smaller LDS share lets 16 waves share a CU.  out[4] = dc,
- * da_1, da_2, da_3. */
+ * 0 only) a ring of 3 slabs, whose smaller LDS share lets 16 waves share a CU; bit 13 (layout
+ * 0 only) at most 8 waves per CU (each work-group padded to 20 KB of LDS); bit 14 (p = 3) the
+ * row-by-row blocks after each matrix's last slab, one 16-byte store per lane and q_1 as a lane
+ * (r, j) holds them after a transpose within its quad (64 bytes of row r per store); bit 15 (p = 3)
+ * gradients in line-q_1 blocks, [i_1][i_2][q_1][i_3][q_2][q_3]: as each q_1 completes, the
+ * tile's values of that q_1 form one contiguous 1 KB block, one 16-byte store per lane.
+ * out[4] = dc, da_1, da_2, da_3. */
 int wqap_adjoint(int parts, int layout, int dtype, int p, const int64_t *n_elem, const void *gM,
                  const void *gK, void *const *out, void *hip_stream);
 

@@ -48,6 +48,7 @@ _SIGS = {
     "wqa_set_final_mode": ([_vp, ctypes.c_int], ctypes.c_int),
     "wqa_set_dispatch_limit": ([_vp, ctypes.c_int64], ctypes.c_int),
     "wqa_set_grid_pitch": ([_vp, ctypes.c_int64], ctypes.c_int),
+    "wqa_set_sample_layout": ([_vp, ctypes.c_int], ctypes.c_int),
     "wqa_assemble_mass": ([_vp, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
     "wqa_assemble_stiffness": ([_vp, ctypes.c_int, _P(_vp), _vp, _vp], ctypes.c_int),
     "wqa_assemble_fused": ([_vp, ctypes.c_int, _vp, _P(_vp), _vp, _vp, _vp], ctypes.c_int),

@@ -39,25 +39,45 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
+def _run_all(cmds, verbose):
+    """Runs the commands side by side; raises if any fails (after all have ended)."""
+    procs = []
+    for cmd in cmds:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+    failed = [cmd for cmd, pr in procs if pr.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+
+
 def build(verbose=False):
     """Compile every source and link paper_1710_01048_amd/libwqa.so (always rebuilds)."""
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    k_obj = os.path.join(BUILD, "wqa_kernels.o")
+    # the kernels source once per part (forward, products, FP32 and FP64 adjoint), the
+    # host code and the probes: independent compilations, run side by side
+    jobs = []
+    k_objs = []
+    for part in range(4):
+        obj = os.path.join(BUILD, f"wqa_kernels_{part}.o")
+        k_objs.append(obj)
+        jobs.append([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *HIP_FLAGS, *inc, f"-DWQA_PART={part}",
+                     "-Wno-unneeded-internal-declaration", "-Wno-unused-function", "-c",
+                     os.path.join(CSRC, "wqa_kernels.hip"), "-o", obj])
     h_obj = os.path.join(BUILD, "wqa_host.o")
-    _run([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *HIP_FLAGS, *inc, "-c",
-          os.path.join(CSRC, "wqa_kernels.hip"), "-o", k_obj], verbose)
-    _run([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *HIP_FLAGS, *inc, "-c",
-          os.path.join(CSRC, "wqa_host.cpp"), "-o", h_obj], verbose)
+    jobs.append([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *HIP_FLAGS, *inc, "-c",
+                 os.path.join(CSRC, "wqa_host.cpp"), "-o", h_obj])
+    ptmp = PROBES + ".tmp%d" % os.getpid()
+    jobs.append([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *HIP_FLAGS, *inc, "-shared",
+                 os.path.join(CSRC, "wqa_probes.hip"), "-o", ptmp])
+    _run_all(jobs, verbose)
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, k_obj, h_obj], verbose)
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *k_objs, h_obj], verbose)
     os.replace(tmp, LIB)
     # the memory-pattern probes (measurement only; the bench loads them)
-    tmp = PROBES + ".tmp%d" % os.getpid()
-    _run([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *HIP_FLAGS, *inc, "-shared",
-          os.path.join(CSRC, "wqa_probes.hip"), "-o", tmp], verbose)
-    os.replace(tmp, PROBES)
+    os.replace(ptmp, PROBES)
     return LIB
 
 

@@ -550,6 +550,7 @@ struct wqa_ctx {
     bool banded[2][wqa::kMaxDim] = {};
     int64_t max_tasks = wqa::kMaxTasksPerDispatch;      // wave tasks per kernel dispatch
     int64_t pitch = 0;                                  // grid line pitch (0: dense, N of the last direction)
+    int samples = WQA_SAMPLES_GRID;                     // layout of the sample buffers
     // device copies
     void *dev = nullptr;
     size_t dev_bytes = 0;
@@ -886,6 +887,7 @@ wqa_status wqa_set_space(wqa_ctx *c, int dim, int degree, const int64_t *n_elem)
     c->dim = dim;
     c->p = degree;
     c->pitch = 0;
+    c->samples = WQA_SAMPLES_GRID;
     for (int k = 0; k < wqa::kMaxDim; ++k) {
         c->nel[k] = k < dim ? n_elem[k] : 0;
         c->n[k] = k < dim ? n_elem[k] + degree : 0;
@@ -1031,7 +1033,20 @@ wqa_status wqa_set_grid_pitch(wqa_ctx *c, int64_t pitch) {
     if (pitch != 0 && (pitch < Nd || pitch % 4 != 0))
         return fail(WQA_EINVAL, "wqa_set_grid_pitch: pitch %lld (need 0, or a multiple of 4 of at least %lld)",
                     (long long)pitch, (long long)Nd);
+    if (pitch != 0 && c->samples != WQA_SAMPLES_GRID)
+        return fail(WQA_ESTATE, "wqa_set_grid_pitch: the pitch applies to the grid layout only (samples by row)");
     c->pitch = pitch;
+    return ok();
+}
+
+wqa_status wqa_set_sample_layout(wqa_ctx *c, int layout) {
+    if (!c) return fail(WQA_EINVAL, "wqa_set_sample_layout: NULL context");
+    if (!c->have_space) return fail(WQA_ESTATE, "wqa_set_sample_layout: call wqa_set_space first");
+    if (layout != WQA_SAMPLES_GRID && layout != WQA_SAMPLES_ROWS)
+        return fail(WQA_EINVAL, "wqa_set_sample_layout: layout %d", layout);
+    if (layout != WQA_SAMPLES_GRID && c->pitch != 0)
+        return fail(WQA_ESTATE, "wqa_set_sample_layout: a grid pitch is set (reset it to 0 first)");
+    c->samples = layout;
     return ok();
 }
 
@@ -1064,6 +1079,7 @@ void fill(const wqa_ctx *c, wqa::DevSpace &sp, wqa::DevTabs &tb, wqa_dtype dtype
     sp.d = c->dim;
     sp.p = c->p;
     sp.ld = c->pitch ? c->pitch : c->N[c->dim - 1];
+    sp.rows = c->samples == WQA_SAMPLES_ROWS ? 1 : 0;
     sp.band = 0;
     for (int k = 0; k < c->dim; ++k)
         if (c->banded[WQA_MASS][k] && c->banded[WQA_STIFFNESS][k]) sp.band |= 1 << k;

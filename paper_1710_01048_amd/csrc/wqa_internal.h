@@ -19,6 +19,7 @@ struct DevSpace {
     int64_t n[kMaxDim];   // basis functions per direction
     int64_t N[kMaxDim];   // grid points per direction (n * (p + 1))
     int64_t ld;           // values between consecutive grid lines of the last direction (>= N[d-1])
+    int rows;             // 1: samples stored row by row ([rows][Q^d]); 0: on the grid
 };
 
 // Largest number of wave tasks one kernel dispatch takes by default; larger launches

@@ -44,8 +44,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // FINAL 0: plain fused multiply-add in T.
 // FINAL 1: compensated dot product in FP32 registers (Ogita, Rump and Oishi's Dot2:
 //          error-free products via FMA, error-free sums, errors summed separately).
-// FINAL 2: compensated through an FP64 accumulator: the FP32 factor times the FP64 table
-//          entry, summed in FP64, rounded once (a v_fma_f64 issues at the FP32 rate).
+// FINAL 2: mixed precision through an FP64 accumulator: the FP32 factor times the FP64
+//          table entry, summed in FP64, rounded once (a v_fma_f64 issues at the FP32 rate).
 template <typename T, int FINAL>
 struct Acc {
     T s = T(0);
@@ -57,7 +57,10 @@ template <>
 struct Acc<float, 1> {
     float p = 0.f, e = 0.f;
     bool first = true;     // resolved at compile time in the unrolled loops
+    // No contraction here: a multiply-add fused by the compiler (p + a * b as one FMA)
+    // would break the error-free transformations, and could differ between call sites.
     __device__ __forceinline__ void add(float a, float b) {
+#pragma clang fp contract(off)
         const float h = a * b;
         const float r = __builtin_fmaf(a, b, -h);      // a * b = h + r exactly
         if (first) {                                   // the sum so far is h itself
@@ -72,7 +75,10 @@ struct Acc<float, 1> {
         p = t;
         e += q + r;
     }
-    __device__ __forceinline__ float get() const { return p + e; }
+    __device__ __forceinline__ float get() const {
+#pragma clang fp contract(off)
+        return p + e;
+    }
 };
 
 template <>
@@ -81,6 +87,17 @@ struct Acc<float, 2> {
     __device__ __forceinline__ void add(double a, float b) { s = __builtin_fma(a, (double)b, s); }
     __device__ __forceinline__ float get() const { return (float)s; }
 };
+
+// A copy of v the compiler cannot see through.  The adjoint's FP64-accumulated final pass
+// passes each slab result through it at every use, so that the conversion to FP64 happens
+// per use: one conversion shared by the outputs that read the same slab result would keep
+// an FP64 copy of every live one (measured: 147 instead of 109 VGPRs in the banded kernel,
+// 214 instead of 129 in the other).
+template <typename T>
+__device__ __forceinline__ T opaque(T v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
 
 // Table element type used by the final pass.
 template <typename T, int FINAL> struct FinalTab { using type = T; };
@@ -251,6 +268,32 @@ __device__ __forceinline__ Tile make_tile(const DevSpace &sp, int64_t task, int 
     return t;
 }
 
+// Where the sample of point (q1[, q2], ql) of a lane's row lies in a sample buffer: a
+// wave-uniform offset (uniform(q1, q2)) plus the lane's own (lo).  On the grid the row's
+// point is ((i1 Q + q1), (i2 Q + q2), il Q + ql); stored row by row it is value
+// ((q1 Q) + q2) Q + ql of the row's block of Q^d.
+template <int D, int P>
+struct SampleIndex {
+    static constexpr int Q = P + 1, QD = (D == 3) ? Q * Q * Q : Q * Q;
+    int64_t u0, s1, s2;    // uniform part: u0 + q1 s1 + q2 s2
+    uint32_t lo;
+    __device__ __forceinline__ SampleIndex(const DevSpace &sp, const Tile &t, int ql) {
+        if (sp.rows) {
+            u0 = t.row0 * QD;
+            s1 = (D == 3) ? Q * Q : Q;
+            s2 = Q;
+            lo = (uint32_t)((t.il - t.t0) * QD + ql);
+        } else {
+            const int64_t N2 = (D == 3) ? sp.N[1] : sp.ld, N3 = (D == 3) ? sp.ld : 1;
+            s1 = N2 * N3;
+            s2 = N3;
+            u0 = (D == 3) ? (t.i1 * Q * N2 + t.i2 * Q) * N3 : t.i1 * Q * N2;
+            lo = (uint32_t)(t.il * Q + ql);
+        }
+    }
+    __device__ __forceinline__ int64_t uniform(int q1, int q2) const { return u0 + q1 * s1 + q2 * s2; }
+};
+
 // Whether every leading index of the tile's line is interior and its direction's tables
 // banded (see in_band).
 template <int D, int P>
@@ -285,6 +328,48 @@ struct Forward {
 
     template <int NF>
     __device__ __forceinline__ void stage_fields(const T *const (&f)[NF]) const {
+        if (sp.rows) stage_rows<NF>(f);
+        else stage_grid<NF>(f);
+    }
+
+    // Samples stored row by row: the tile's samples of a field are one contiguous block of
+    // rows_here x Q^d values; value (r, g, q) of it (g the leading nodes, q the last one)
+    // goes to the same LDS slot as from the grid, g R Q + r Q + q.
+    template <int NF>
+    __device__ __forceinline__ void stage_rows(const T *const (&f)[NF]) const {
+        constexpr int QD = NG * Q;
+        constexpr int U = (QD * (int)sizeof(T)) % 16 == 0 && Q % (16 / (int)sizeof(T)) == 0 ? 16 / (int)sizeof(T) : 1;
+        constexpr int TOT = R * QD / U;                 // loads per field
+        constexpr int IT = (TOT + 63) / 64;
+        using VT = T __attribute__((ext_vector_type(U)));
+        int lds[IT];
+        bool ok[IT];
+        const int n = t.rows_here * QD;
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = (lane + 64 * it) * U;
+            const int r = e / QD, w = e - r * QD, g = w / Q;
+            ok[it] = e < n;
+            lds[it] = g * R * Q + r * Q + (w - g * Q);
+        }
+        const int64_t base = t.row0 * QD;
+        VT v[NF][IT];
+#pragma unroll
+        for (int m = 0; m < NF; ++m)
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int e = ok[it] ? (lane + 64 * it) * U : 0;
+                v[m][it] = *reinterpret_cast<const VT *>(f[m] + base + e);
+            }
+#pragma unroll
+        for (int m = 0; m < NF; ++m)
+#pragma unroll
+            for (int it = 0; it < IT; ++it)
+                if (lane + 64 * it < TOT) *reinterpret_cast<VT *>(stage + m * FSZ + lds[it]) = ok[it] ? v[m][it] : VT(0);
+    }
+
+    template <int NF>
+    __device__ __forceinline__ void stage_grid(const T *const (&f)[NF]) const {
         constexpr int U = (Q * (int)sizeof(T)) % 16 == 0 ? 16 / (int)sizeof(T) : 1;   // values per load
         constexpr int PER = R * Q / U;                  // loads per line
         constexpr int TOT = NG * PER;                   // loads per field
@@ -630,7 +715,8 @@ __device__ __forceinline__ uint32_t lds_addr(const T *p) {
 // LB: every row of the tile is at least P from both ends of its line and the last
 // direction's tables are banded, so a lane with node q_d only meets the slots
 // s_d = q_d .. q_d + P of each slab row (tl then holds those P+1 table entries).
-template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R, int RING, bool LB = false>
+template <typename T, int P, int D, int FINAL, bool BAND, int WPB, int R, int RING, bool LB = false,
+          bool ROWS = false>
 struct Adjoint {
     static constexpr int Q = P + 1, S = 2 * P + 1;
     static constexpr int SL = (D == 3) ? S * S : S;     // slots of one s1 slab
@@ -645,6 +731,12 @@ struct Adjoint {
     static_assert(RING >= 2 && RING <= 4 && (RING - 1) * NPF < 64, "ring depth");
     static constexpr bool LIMIT = sizeof(T) == 8;
     static constexpr int NT = LB ? P + 1 : S;            // last-direction table entries per lane
+    // Samples stored row by row: the tile's gradients of a field leave through the ring
+    // buffer of the run's last slab, free from its contraction until the next matrix's first
+    // acquire refills it, CH rows at a time.
+    static constexpr int QD = (D == 3) ? Q * Q * Q : Q * Q;
+    static constexpr int CH = (SLOT * 4 / (int)sizeof(T)) / QD < R ? (SLOT * 4 / (int)sizeof(T)) / QD : R;
+    static_assert(CH >= 1, "a ring buffer holds at least one row of gradients");
 
     const DevSpace &sp;
     const Tile &t;
@@ -789,13 +881,73 @@ struct Adjoint {
                 Acc<T, FINAL> a;
 #pragma unroll
                 for (int s1 = 0; s1 < S; ++s1)
-                    if (!BAND || in_band<P>(q1, s1)) a.add(f1m[q1 * S + s1], Z[m][s1][q2]);
+                    if (!BAND || in_band<P>(q1, s1)) a.add(f1m[q1 * S + s1], fin(Z[m][s1][q2]));
                 int64_t off;     // wave-uniform part; the lane adds il * Q + ql
                 if constexpr (D == 3) off = ((t.i1 * Q + q1) * N2 + t.i2 * Q + q2) * N3;
                 else off = (t.i1 * Q + q1) * N2;
                 (out[m] + off)[lo] = a.get();
             }
         }
+    }
+
+    // Samples stored row by row: per field, the values val(m, q1, q2) of the lane's point
+    // column go to the staging buffer -- value w = (q1 Q + q2) Q + ql of row r at
+    // r QD + (w ^ swz(r)), a swizzle that spreads one store instruction over the banks --
+    // and the tile's block of rows_here x QD values (CH rows at a time) leaves with 16-byte
+    // stores, consecutive lanes at consecutive addresses.
+    // a slab result as the final pass takes it (see opaque)
+    static __device__ __forceinline__ T fin(T z) {
+        if constexpr (FINAL == 2 && sizeof(T) == 4) return opaque(z);
+        else return z;
+    }
+
+    static __device__ __forceinline__ int swz(int r) {
+        constexpr int MASK = (QD & (QD - 1)) == 0 && QD >= 16 ? (QD / 4 < 16 ? QD / 4 : 16) - 1 : 0;
+        return (r & MASK) << 2;
+    }
+
+    template <int NSET, class F>
+    __device__ __forceinline__ void store_rows(int pos_last, F val, T *const (&out)[NSET]) const {
+        constexpr int VEC = (QD * (int)sizeof(T)) % 16 == 0 ? 16 / (int)sizeof(T) : 1;
+        using V = T __attribute__((ext_vector_type(VEC)));
+        T *stg = reinterpret_cast<T *>(ring + (pos_last % RING) * SLOT);
+#pragma unroll
+        for (int m = 0; m < NSET; ++m) {
+#pragma unroll
+            for (int c0 = 0; c0 < R; c0 += CH) {
+                const int rr = t.r - c0;
+                if (t.active && rr >= 0 && rr < CH) {
+#pragma unroll
+                    for (int q1 = 0; q1 < Q; ++q1)
+#pragma unroll
+                        for (int q2 = 0; q2 < NQ2; ++q2)
+                            stg[rr * QD + (((q1 * NQ2 + q2) * Q + ql) ^ swz(rr))] = val(m, q1, q2);
+                }
+                wave_lds_sync();
+                const int nr = t.rows_here - c0 < CH ? t.rows_here - c0 : CH;
+                if (nr > 0) {
+                    T *dst = out[m] + (t.row0 + c0) * QD;
+                    const int nv = nr * QD / VEC;
+                    for (int k = lane; k < nv; k += 64) {
+                        const int e = k * VEC, r = e / QD, w = e - r * QD;
+                        *reinterpret_cast<V *>(dst + e) = *reinterpret_cast<const V *>(stg + r * QD + (w ^ swz(r)));
+                    }
+                }
+                wave_lds_sync();
+            }
+        }
+    }
+
+    // Final pass of output (m, q1, q2): sum over s1 of the first-direction table entry times
+    // the slab result, s1 ascending.
+    template <int NSET, int NZ>
+    __device__ __forceinline__ T final_q1(const cptr<FT> &f1m, int q1, int q2, const T (&Z)[NSET][NZ][NQ2],
+                                          int m) const {
+        Acc<T, FINAL> a;
+#pragma unroll
+        for (int s1 = 0; s1 < S; ++s1)
+            if (!BAND || in_band<P>(q1, s1)) a.add(f1m[q1 * S + s1], fin(Z[m][s1][q2]));
+        return a.get();
     }
 
     // The slabs of one matrix (stream positions pos0 ...), then the final pass over s1 and
@@ -807,8 +959,10 @@ struct Adjoint {
                                         const cptr<FT> (&f1)[NSET], T *const (&out)[NSET]) const {
         constexpr bool RUNNING = (FINAL == 0);
         constexpr int NZ = RUNNING ? 1 : S;
+        constexpr bool EARLY = BAND && !RUNNING;         // outputs final once s1 = q1 + P
         T Z[NSET][NZ][NQ2];
         T acc[NSET][RUNNING ? Q : 1][NQ2];
+        T O[NSET][EARLY && ROWS ? Q : 1][NQ2];          // finished outputs held for the block store
 #pragma unroll
         for (int m = 0; m < NSET; ++m) {
 #pragma unroll
@@ -852,12 +1006,35 @@ struct Adjoint {
                 }
             }
             // Banded tiles: output q1 has all its slabs once s1 = q1 + P, so it is finished
-            // and stored right away, and only P + 1 slab results stay live
-            if constexpr (BAND && !RUNNING) {
+            // right away (on the grid also stored), and only P + 1 slab results stay live
+            if constexpr (EARLY && !ROWS) {
                 if (s1 >= P && t.active) emit_q1<NSET, NZ>(s1 - P, f1, Z, out);
             }
+            if constexpr (EARLY && ROWS) {
+                if (s1 >= P) {
+#pragma unroll
+                    for (int m = 0; m < NSET; ++m) {
+                        const cptr<FT> f1m = fresh(f1[m]);
+#pragma unroll
+                        for (int q2 = 0; q2 < NQ2; ++q2) O[m][s1 - P][q2] = final_q1<NSET, NZ>(f1m, s1 - P, q2, Z, m);
+                    }
+                }
+            }
         }
-        if constexpr (BAND && !RUNNING) return;
+        if constexpr (EARLY && !ROWS) return;
+        if constexpr (ROWS) {
+            const int pos_last = pos0 + n_s1 - 1;
+            if constexpr (RUNNING) {
+                store_rows<NSET>(pos_last, [&](int m, int q1, int q2) { return acc[m][q1][q2]; }, out);
+            } else if constexpr (EARLY) {
+                store_rows<NSET>(pos_last, [&](int m, int q1, int q2) { return O[m][q1][q2]; }, out);
+            } else {
+                store_rows<NSET>(pos_last, [&](int m, int q1, int q2) {
+                    return final_q1<NSET, NZ>(fresh(f1[m]), q1, q2, Z, m);
+                }, out);
+            }
+            return;
+        }
         if (t.active) {
             const int64_t N2 = (D == 3) ? sp.N[1] : sp.ld, N3 = (D == 3) ? sp.ld : 1;
             const uint32_t lo = (uint32_t)(t.il * Q + ql);
@@ -875,7 +1052,7 @@ struct Adjoint {
                             Acc<T, FINAL> a;
 #pragma unroll
                             for (int s1 = 0; s1 < S; ++s1)
-                                if (!BAND || in_band<P>(q1, s1)) a.add(f1m[q1 * S + s1], Z[m][s1][q2]);
+                                if (!BAND || in_band<P>(q1, s1)) a.add(f1m[q1 * S + s1], fin(Z[m][s1][q2]));
                             v = a.get();
                         }
                         int64_t off;     // wave-uniform part; the lane adds il * Q + ql
@@ -889,12 +1066,12 @@ struct Adjoint {
     }
 };
 
-template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R, int RING, bool LB = false>
+template <typename T, int P, int D, int WHAT, int FINAL, bool BAND, int WPB, int R, int RING, bool LB, bool ROWS>
 __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &tb, const Tile &t, uint32_t *ring,
                                              int lane, const T *__restrict__ gM, const T *__restrict__ gK,
                                              T *__restrict__ dc, T *__restrict__ da0, T *__restrict__ da1,
                                              T *__restrict__ da2) {
-    using A = Adjoint<T, P, D, FINAL, BAND, WPB, R, RING, LB>;
+    using A = Adjoint<T, P, D, FINAL, BAND, WPB, R, RING, LB, ROWS>;
     constexpr int Q = A::Q, S = A::S, NT = A::NT;
     using FT = typename A::FT;
     constexpr bool DO_M = (WHAT & kWhatM) != 0, DO_K = (WHAT & kWhatK) != 0;
@@ -974,15 +1151,15 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
 
 // INTERIOR: the banded kernel over the interior lines.  Otherwise the full loops over
 // the lines of line_set (the boundary lines, or every line when some leading direction's
-// tables are not banded).
-template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int RING, bool INTERIOR>
+// tables are not banded).  ROWS: gradients stored row by row.
+template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int RING, bool INTERIOR, bool ROWS>
 __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
     DevSpace sp, DevTabs tb, const T *__restrict__ gM, const T *__restrict__ gK,
     T *__restrict__ dc, T *__restrict__ da0, T *__restrict__ da1, T *__restrict__ da2,
     int64_t task0, int64_t n_tasks, int tiles_per_line, int line_set) {
     constexpr int Q = P + 1;
     constexpr int R = 64 / Q;                      // rows per wave tile
-    using A = Adjoint<T, P, D, FINAL, false, WPB, R, RING>;
+    using A = Adjoint<T, P, D, FINAL, false, WPB, R, RING, false, ROWS>;
     __shared__ __align__(16) uint32_t ring[WPB][RING * A::SLOT];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
@@ -995,11 +1172,11 @@ __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
     // interior kernel: tiles whose rows are all banded in the last direction too take the
     // short last-direction loops (each tile picks its code path)
     if (INTERIOR && ((sp.band >> (D - 1)) & 1) && t.t0 >= P && t.t0 + t.rows_here + P <= t.nl)
-        adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING, INTERIOR>(sp, tb, t, ring[wave], lane, gM, gK, dc,
-                                                                           da0, da1, da2);
+        adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING, INTERIOR, ROWS>(sp, tb, t, ring[wave], lane, gM,
+                                                                                 gK, dc, da0, da1, da2);
     else
-        adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING, false>(sp, tb, t, ring[wave], lane, gM, gK, dc,
-                                                                        da0, da1, da2);
+        adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING, false, ROWS>(sp, tb, t, ring[wave], lane, gM, gK,
+                                                                              dc, da0, da1, da2);
 }
 
 // --------------------------------------------------------------------------------------
@@ -1100,20 +1277,14 @@ struct Apply {
 #pragma unroll
                         for (int q2 = 0; q2 < NQ2; ++q2) X[m][q1][q2] = fma(Z[m][q2], t1[m][q1 * S + s1], X[m][q1][q2]);
         }
-        const int64_t N2 = (D == 3) ? sp.N[1] : sp.ld, N3 = (D == 3) ? sp.ld : 1;
-        const uint32_t lo = (uint32_t)(t.il * Q + ql);
+        const SampleIndex<D, P> at(sp, t, ql);
         T acc = T(0);
 #pragma unroll
         for (int m = 0; m < NSET; ++m)
 #pragma unroll
             for (int q1 = 0; q1 < Q; ++q1)
 #pragma unroll
-                for (int q2 = 0; q2 < NQ2; ++q2) {
-                    int64_t off;     // wave-uniform part; the lane adds il * Q + ql
-                    if constexpr (D == 3) off = ((t.i1 * Q + q1) * N2 + t.i2 * Q + q2) * N3;
-                    else off = (t.i1 * Q + q1) * N2;
-                    acc = fma((f[m] + off)[lo], X[m][q1][q2], acc);
-                }
+                for (int q2 = 0; q2 < NQ2; ++q2) acc = fma((f[m] + at.uniform(q1, q2))[at.lo], X[m][q1][q2], acc);
         return acc;
     }
 };
@@ -1312,14 +1483,18 @@ hipError_t run_adjoint(const DevSpace &sp, const DevTabs &tb, const void *gM, co
         const dim3 block(64 * WPB);
         const hipError_t e = split_launch(tasks, max_tasks, WPB, [&](int64_t t0, dim3 grid) {
             const int64_t end = t0 + (int64_t)grid.x * WPB < tasks ? t0 + (int64_t)grid.x * WPB : tasks;
-            if (set == 0)
-                hipLaunchKernelGGL((adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, true>), grid, block, 0, st, sp,
-                                   tb, (const T *)gM, (const T *)gK, (T *)dc, d0, d1, d2, t0, end, tiles,
-                                   (int)kLinesInterior);
-            else
-                hipLaunchKernelGGL((adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, false>), grid, block, 0, st, sp,
-                                   tb, (const T *)gM, (const T *)gK, (T *)dc, d0, d1, d2, t0, end, tiles,
-                                   other_set);
+            const int ls = set == 0 ? (int)kLinesInterior : other_set;
+            auto go = [&](auto kernel) {
+                hipLaunchKernelGGL(kernel, grid, block, 0, st, sp, tb, (const T *)gM, (const T *)gK, (T *)dc, d0, d1,
+                                   d2, t0, end, tiles, ls);
+            };
+            if (set == 0) {
+                if (sp.rows) go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, true, true>);
+                else go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, true, false>);
+            } else {
+                if (sp.rows) go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, false, true>);
+                else go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, false, false>);
+            }
         });
         if (e != hipSuccess) return e;
     }
@@ -1435,24 +1610,43 @@ hipError_t adj_shape(int final_mode, int what, const DevSpace &sp, const DevTabs
 
 }  // namespace
 
+// The file is compiled once per part (WQA_PART 0 to 3: forward, products, FP32 adjoint,
+// FP64 adjoint), so that the sets of kernels build in parallel.
+#if !defined(WQA_PART) || WQA_PART == 0
 hipError_t launch_forward(int dtype, int final_mode, int what, const DevSpace &sp, const DevTabs &tb,
                           const void *c, const void *const *a, void *M, void *K, hipStream_t stream,
                           int64_t max_tasks) {
     if (dtype == 0) return fwd_shape<float>(final_mode, what, sp, tb, c, a, M, K, stream, max_tasks);
     return fwd_shape<double>(final_mode, what, sp, tb, c, a, M, K, stream, max_tasks);
 }
+#endif
 
+#if !defined(WQA_PART) || WQA_PART == 1
 hipError_t launch_apply(int dtype, int what, bool ones, const DevSpace &sp, const DevTabs &tb, const void *c,
                         const void *const *a, const void *x, void *y, hipStream_t stream, int64_t max_tasks) {
     if (dtype == 0) return apply_shape<float>(what, ones, sp, tb, c, a, x, y, stream, max_tasks);
     return apply_shape<double>(what, ones, sp, tb, c, a, x, y, stream, max_tasks);
 }
+#endif
 
+// the adjoint's FP32 and FP64 kernels in parts of their own (WQA_PART 2 and 3)
+hipError_t launch_adjoint_f64(int final_mode, int what, const DevSpace &sp, const DevTabs &tb, const void *gM,
+                              const void *gK, void *dc, void *const *da, hipStream_t stream, int64_t max_tasks);
+
+#if !defined(WQA_PART) || WQA_PART == 2
 hipError_t launch_adjoint(int dtype, int final_mode, int what, const DevSpace &sp, const DevTabs &tb,
                           const void *gM, const void *gK, void *dc, void *const *da, hipStream_t stream,
                           int64_t max_tasks) {
     if (dtype == 0) return adj_shape<float>(final_mode, what, sp, tb, gM, gK, dc, da, stream, max_tasks);
+    return launch_adjoint_f64(final_mode, what, sp, tb, gM, gK, dc, da, stream, max_tasks);
+}
+#endif
+
+#if !defined(WQA_PART) || WQA_PART == 3
+hipError_t launch_adjoint_f64(int final_mode, int what, const DevSpace &sp, const DevTabs &tb, const void *gM,
+                              const void *gK, void *dc, void *const *da, hipStream_t stream, int64_t max_tasks) {
     return adj_shape<double>(final_mode, what, sp, tb, gM, gK, dc, da, stream, max_tasks);
 }
+#endif
 
 }  // namespace wqa

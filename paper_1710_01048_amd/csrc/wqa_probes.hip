@@ -190,6 +190,33 @@ __global__ __launch_bounds__(64) void adjoint_tile_probe(Grid3 g, const T *__res
                 *reinterpret_cast<V4 *>(outs[m] + (row0 + r) * Q * Q * Q + q1 * Q * Q + j * Q) = V4{acc, acc, acc, acc};
             return;
         }
+        if (g.rowpts == 5) {
+            // line-q1 blocks ([i1][i2][q1][i3][q2][q3], p = 3): as each q1 completes, the
+            // tile's (i3, q2, q3) values of that q1 are one contiguous 1 KB block, written
+            // with one 16-byte store per lane (lane (r, j): q2 = j, q3 = 0..3 after a
+            // transpose within its quad)
+            if (!active) return;
+            using V4 = T __attribute__((ext_vector_type(4)));
+            const int64_t line = row0 / g.n[2];
+            for (int m = 0; m < nset; ++m)
+                *reinterpret_cast<V4 *>(outs[m] + ((line * Q + q1) * g.n[2] + t0) * Q * Q + lane * 4) =
+                    V4{acc, acc, acc, acc + T(q1)};
+            return;
+        }
+        if (g.rowpts == 4) {
+            // the same blocks after each matrix's last slab, in the order a lane (r, q_3)
+            // would hold them after a transpose within its quad: one 16-byte store per q1,
+            // the (p+1)^2 values of row r with q2 = j (64 bytes per row and store)
+            if (q1 != Q - 1 || !active) return;
+            using V4 = T __attribute__((ext_vector_type(4)));
+            const int r = lane / Q, j = lane - r * Q;
+            for (int m = 0; m < nset; ++m)
+#pragma unroll
+                for (int a1 = 0; a1 < Q; ++a1)
+                    *reinterpret_cast<V4 *>(outs[m] + (row0 + r) * Q * Q * Q + (a1 * Q + j) * Q) =
+                        V4{acc, acc, acc, acc + T(a1)};
+            return;
+        }
         if (g.rowpts) {
             // the tile's rows of each field are one contiguous block of rows_here (p+1)^3
             // values: written with 16-byte stores once per matrix run
@@ -444,12 +471,16 @@ int launch_adjoint_bulk(const Grid3 &g, const void *gM, const void *gK, void *co
 
 template <typename T, int P, int PARTS, bool DEFER = false, int RING_ = 0>
 int launch_adjoint_tile(const Grid3 &g, const void *gM, const void *gK, void *const *out, hipStream_t st,
-                        int order) {
+                        int order, int cap8 = 0) {
     constexpr int R = AdjShape<T, P>::R;
     const int tiles = (int)((g.n[2] + R - 1) / R);
     const int64_t tasks = g.n[0] * g.n[1] * tiles;
     if (tasks >= (int64_t(1) << 31) / 64) return -1;
-    hipLaunchKernelGGL((adjoint_tile_probe<T, P, PARTS, DEFER, RING_>), dim3((unsigned)tasks), dim3(64), 0, st, g,
+    // cap8: dynamic LDS that brings each work-group to 20 KB, so that at most 8 share a CU
+    using A = AdjShape<T, P, RING_>;
+    constexpr int kStatic = A::RING * A::SLOT * 4;
+    const size_t dyn = (cap8 && kStatic < 20480) ? (size_t)(20480 - kStatic) : 0;
+    hipLaunchKernelGGL((adjoint_tile_probe<T, P, PARTS, DEFER, RING_>), dim3((unsigned)tasks), dim3(64), dyn, st, g,
                        (const T *)gM, (const T *)gK, (T *)out[0], (T *)out[1], (T *)out[2], (T *)out[3], tasks,
                        tiles, order);
     return hipGetLastError() == hipSuccess ? 0 : -5;
@@ -478,8 +509,11 @@ int adjoint_parts(int parts, int layout, const Grid3 &g, const void *gM, const v
     if (layout & 1024) gp.rowpts = 2;                        // ... each q1 as it completes (p = 3)
     if (layout & 2048) gp.rowpts = 3;                        // ... after the run, 4-byte stores
     const bool ring3 = (layout & 4096) != 0;                 // a ring of 3 slabs (more waves per CU)
+    const int cap8 = (layout & 8192) ? 1 : 0;                // at most 8 waves per CU
+    if (layout & 16384) gp.rowpts = 4;                       // row blocks in the lanes' order
+    if (layout & 32768) gp.rowpts = 5;                       // line-q1 blocks as each q1 completes
     layout &= 63;
-    if (layout == 0 && (ring3 || gp.pitch != g.N[2] || gp.rowpts)) {
+    if (layout == 0 && (ring3 || cap8 || gp.pitch != g.N[2] || gp.rowpts)) {
         if (ring3) {
             switch (parts) {
                 case 2: return launch_adjoint_tile<T, P, 2, false, 3>(gp, gM, gK, out, st, order);
@@ -488,8 +522,8 @@ int adjoint_parts(int parts, int layout, const Grid3 &g, const void *gM, const v
             }
         }
         switch (parts) {
-            case 2: return launch_adjoint_tile<T, P, 2>(gp, gM, gK, out, st, order);
-            case 3: return launch_adjoint_tile<T, P, 3>(gp, gM, gK, out, st, order);
+            case 2: return launch_adjoint_tile<T, P, 2>(gp, gM, gK, out, st, order, cap8);
+            case 3: return launch_adjoint_tile<T, P, 3>(gp, gM, gK, out, st, order, cap8);
             default: return -1;
         }
     }
@@ -695,7 +729,7 @@ int wqap_fronts(void *dst, int k, int64_t spacing, int64_t per_front, void *stre
 int wqap_adjoint(int parts, int layout, int dtype, int p, const int64_t *n_elem, const void *gM, const void *gK,
                  void *const *out, void *stream) {
     if (!geometry_ok(dtype, p, n_elem) || layout < 0 || (layout & 63) > 49 || ((layout >> 6) & 3) > 2 ||
-        layout >= 8192 || !out)
+        layout >= 65536 || ((layout & (16384 | 32768)) && p != 3) || !out)
         return -1;
     if (((parts & 1) && (!gM || !gK)) || ((parts & 2) && (!out[0] || !out[1] || !out[2] || !out[3]))) return -1;
     const Grid3 g = grid_of(p, n_elem);

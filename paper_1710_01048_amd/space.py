@@ -63,7 +63,9 @@ class Space:
         check(lib.wqa_query(self._ctx, ctypes.byref(rows), ctypes.byref(slots), ctypes.byref(pts), dims))
         self.n_rows, self.slots_per_row, self.points_per_row = rows.value, slots.value, pts.value
         self.grid_shape = tuple(dims[k] for k in range(self.dim))
-        self.buffer_shape = self.grid_shape           # grid buffers: lines padded to the pitch
+        self.buffer_shape = self.grid_shape           # sample buffers: grid lines padded to the pitch,
+        self.pitch = 0                                # or [rows, points_per_row] stored row by row
+        self.sample_layout = "grid"
         self.n_basis = tuple(e + self.degree for e in self.n_elem)
 
     def __del__(self):
@@ -117,7 +119,42 @@ class Space:
         direction, the first N_d of them the grid (0: dense).  buffer_shape follows."""
         check(lib.wqa_set_grid_pitch(self._ctx, int(pitch)))
         last = self.grid_shape[-1] if pitch == 0 else int(pitch)
+        self.pitch = int(pitch)
         self.buffer_shape = self.grid_shape[:-1] + (last,)
+
+    def set_sample_layout(self, layout):
+        """'grid' (the default) or 'rows': every sample buffer (fields, gradients, f)
+        then holds [n_rows, points_per_row], the points each row owns as one block
+        (see rows_from_grid).  buffer_shape follows."""
+        code = {"grid": 0, "rows": 1}.get(layout)
+        if code is None:
+            raise ValueError("layout must be 'grid' or 'rows'")
+        check(lib.wqa_set_sample_layout(self._ctx, code))
+        self.sample_layout = layout
+        if code:
+            self.buffer_shape = (self.n_rows, self.points_per_row)
+        else:
+            self.buffer_shape = self.grid_shape[:-1] + (self.pitch or self.grid_shape[-1],)
+
+    def rows_from_grid(self, t):
+        """A dense grid-shaped tensor's values in the row layout: row i's block holds its
+        points (i_k Q + q_k)_k, q_1 slowest (a permutation, made with torch)."""
+        Q = self.degree + 1
+        split = []
+        for n in self.n_basis:
+            split += [n, Q]
+        v = t.reshape(split)
+        v = v.permute(*range(0, 2 * self.dim, 2), *range(1, 2 * self.dim, 2))
+        return v.reshape(self.n_rows, self.points_per_row).contiguous()
+
+    def grid_from_rows(self, t):
+        """The inverse of rows_from_grid: a [n_rows, points_per_row] tensor on the grid."""
+        Q = self.degree + 1
+        v = t.reshape(*self.n_basis, *([Q] * self.dim))
+        order = []
+        for k in range(self.dim):
+            order += [k, self.dim + k]
+        return v.permute(*order).reshape(self.grid_shape).contiguous()
 
     def set_dispatch_limit(self, max_tasks):
         """Wave tasks per kernel dispatch (0: the default); larger launches are split."""
@@ -266,8 +303,8 @@ class WQAssemble(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, space, c, *a):
-        if space.buffer_shape != space.grid_shape:
-            raise ValueError("WQAssemble needs dense grid buffers (grid pitch 0): padding would get no gradient")
+        if space.pitch != 0:
+            raise ValueError("WQAssemble needs dense sample buffers (grid pitch 0): padding would get no gradient")
         ctx.space = space
         ctx.shapes = (c.shape,) + tuple(x.shape for x in a)     # grid-shaped or flat
         c = c.contiguous()

@@ -7,6 +7,7 @@ import re
 
 import numpy as np
 import pytest
+import torch
 
 from oracle import assembly as oa
 from oracle import bspline as ob
@@ -221,3 +222,48 @@ def test_grid_pitch_arguments(wqa):
     assert wqa.lib.wqa_set_grid_pitch(fresh, 64) == -2  # no space yet
     wqa.lib.wqa_destroy(fresh)
     del ctx
+
+
+def test_sample_layout_arguments(wqa):
+    """Row layout: buffer shape [rows, Q^d]; refused while a grid pitch is set and the
+    pitch refused in it; reset by wqa_set_space."""
+    sp = wqa.Space(3, 3, (4, 5, 6), device=None)
+    sp.set_sample_layout("rows")
+    assert sp.buffer_shape == (sp.n_rows, 64)
+    with pytest.raises(wqa.WQAError, match="ESTATE"):
+        sp.set_grid_pitch(64)
+    sp.set_grid_pitch(0)                                  # the dense grid pitch is always fine
+    sp.set_sample_layout("grid")
+    assert sp.buffer_shape == sp.grid_shape
+    sp.set_grid_pitch(64)
+    with pytest.raises(wqa.WQAError, match="ESTATE"):
+        sp.set_sample_layout("rows")
+    sp.set_sample_layout("grid")                          # keeps the padded shape
+    assert sp.buffer_shape == sp.grid_shape[:-1] + (64,)
+    assert wqa.lib.wqa_set_sample_layout(sp._ctx, 2) == -1
+    assert wqa.lib.wqa_set_sample_layout(sp._ctx, -1) == -1
+    # wqa_set_space resets the layout: the pitch is accepted again afterwards
+    sp.set_grid_pitch(0)
+    sp.set_sample_layout("rows")
+    ne = (ctypes.c_int64 * 3)(4, 5, 6)
+    assert wqa.lib.wqa_set_space(sp._ctx, 3, 3, ne) == 0
+    assert wqa.lib.wqa_set_grid_pitch(sp._ctx, 64) == 0
+    fresh = ctypes.c_void_p()
+    assert wqa.lib.wqa_create(ctypes.byref(fresh), -1) == 0
+    assert wqa.lib.wqa_set_sample_layout(fresh, 1) == -2  # no space yet
+    assert wqa.lib.wqa_set_sample_layout(None, 1) == -1
+    wqa.lib.wqa_destroy(fresh)
+
+
+@pytest.mark.parametrize("case", [(3, 3, (4, 5, 6)), (3, 2, (3, 4, 5)), (2, 3, (4, 7)), (2, 2, (5, 3))])
+def test_rows_from_grid_follows_the_row_points(wqa, case):
+    """Space.rows_from_grid puts, in row i's block, the grid values at the points row i
+    owns, in the order the oracle lists them (row_points), and grid_from_rows undoes it."""
+    d, p, n_el = case
+    sp = wqa.Space(d, p, n_el, device=None)
+    g = torch.arange(int(np.prod(sp.grid_shape)), dtype=torch.float64).reshape(sp.grid_shape)
+    r = sp.rows_from_grid(g)
+    want = oa.row_points(p, n_el, np.arange(sp.n_rows))
+    assert r.shape == (sp.n_rows, (p + 1) ** d)
+    assert np.array_equal(r.numpy().astype(np.int64), want)
+    assert torch.equal(sp.grid_from_rows(r), g)
