@@ -232,17 +232,24 @@ def matrix_free(sp, args):
     return out
 
 
-def deformed_cube_forward(wqa, dev, reps=20):
+def deformed_cube_forward(wqa, dev, reps=20, layout="grid"):
     """The 3D C2 cubic forward on 96^3 elements (970,299 rows) with the deformed-cube
     coefficients (det J, det J / J_kk^2 folded into c and a_k): fused M+K, FP32 under every
-    final pass and FP64, event-timed, with the fraction of the 8 TB/s HBM peak."""
+    final pass and FP64, event-timed, with the fraction of the 8 TB/s HBM peak.  layout:
+    the samples on the grid with lines padded to 32 values, or stored row by row."""
     sp = wqa.Space(3, P, (96, 96, 96), device=dev)
-    sp.set_grid_pitch(padded_pitch(sp))
-    out = {"rows": sp.n_rows, "grid_pitch": sp.buffer_shape[-1]}
+    if layout == "grid":
+        sp.set_grid_pitch(padded_pitch(sp))
+        out = {"rows": sp.n_rows, "sample_layout": "grid", "grid_pitch": sp.buffer_shape[-1]}
+        place = lambda t: padded(sp, t)
+    else:
+        sp.set_sample_layout("rows")
+        out = {"rows": sp.n_rows, "sample_layout": "rows"}
+        place = sp.rows_from_grid
     runs = [(torch.float32, f"fp32_{name}", mode) for name, mode in MODES] + [(torch.float64, "fp64", None)]
     for dtype, tag, mode in runs:
         b = 4 if dtype == torch.float32 else 8
-        f = [padded(sp, si.deformed_cube_grid(sp.grid_axes(field), field, dtype, dev)) for field in ["c", 0, 1, 2]]
+        f = [place(si.deformed_cube_grid(sp.grid_axes(field), field, dtype, dev)) for field in ["c", 0, 1, 2]]
         M = torch.empty(sp.n_rows, sp.slots_per_row, dtype=dtype, device=dev)
         K = torch.empty_like(M)
         if mode is not None:
@@ -264,6 +271,44 @@ def deformed_cube_forward(wqa, dev, reps=20):
     for name, _ in MODES:
         out[f"fp32_{name}"]["speedup_vs_fp64"] = out["fp64"]["forward_ms"] / out[f"fp32_{name}"]["forward_ms"]
     sp.set_final_mode(HEADLINE_MODE)
+    return out
+
+
+def row_layout(wqa, dev, args, reps=10):
+    """The headline space's forward and adjoint with the samples stored row by row
+    (wqa_set_sample_layout): FP32 (headline final pass) and FP64, event-timed, mean per
+    call, with the fraction of the 8 TB/s HBM peak (the algorithmic bytes do not depend
+    on the layout)."""
+    def timed(fn):
+        fn()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    sp = wqa.Space(3, P, NEL, device=dev)
+    sp.set_sample_layout("rows")
+    out = {}
+    for dtype in ((torch.float32,) if args.skip_fp64 else (torch.float32, torch.float64)):
+        b = 4 if dtype == torch.float32 else 8
+        nbytes = sp.n_rows * (2 * sp.slots_per_row + 4 * sp.points_per_row) * b
+        f = [sp.rows_from_grid(si.fourier_grid(sp.grid_axes(fl), si.fourier_modes(SEED_FAMILY, fid, 3), dtype, dev))
+             for fid, fl in enumerate(["c", 0, 1, 2])]
+        M = torch.empty(sp.n_rows, sp.slots_per_row, dtype=dtype, device=dev)
+        K = torch.empty_like(M)
+        r = {"forward_ms": timed(lambda: sp.assemble_fused(f[0], f[1:], M, K))}
+        r["forward_frac_of_hbm_peak"] = nbytes / (r["forward_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+        gM = si.upstream_gradient(NEL, P, 1000 * SEED_FAMILY + 1, dtype, dev)
+        gK = si.upstream_gradient(NEL, P, 1000 * SEED_FAMILY + 2, dtype, dev)
+        d = [torch.empty(sp.buffer_shape, dtype=dtype, device=dev) for _ in range(4)]
+        r["adjoint_ms"] = timed(lambda: sp.adjoint(gM, gK, d[0], d[1:]))
+        r["adjoint_frac_of_hbm_peak"] = nbytes / (r["adjoint_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+        out["fp32" if b == 4 else "fp64"] = r
+        del f, M, K, gM, gK, d
+        torch.cuda.empty_cache()
     return out
 
 
@@ -486,7 +531,9 @@ def main():
     assert torch.cuda.is_available(), "needs a HIP device"
     dev = torch.device("cuda:0")
     if args.cube96_only:
-        print(json.dumps({"forward_96cubed_deformed_cube": deformed_cube_forward(wqa, dev)}), flush=True)
+        print(json.dumps({"forward_96cubed_deformed_cube": deformed_cube_forward(wqa, dev),
+                          "forward_96cubed_deformed_cube_rows": deformed_cube_forward(wqa, dev, layout="rows")}),
+              flush=True)
         return
     if args.probe_sweep:
         print(json.dumps({"probe_sweep": probe_sweep(wqa, dev, args.probe_sweep)}), flush=True)
@@ -559,12 +606,16 @@ def main():
         del r64["out"], f64, gM64, gK64
         torch.cuda.empty_cache()
 
-    mfree, cube96 = None, None
+    mfree, cube96, cube96_rows, rows_layout = None, None, None, None
     if not args.headline_only:
         mfree = matrix_free(sp, args)
         log(f"matrix-free: {mfree}")
         cube96 = deformed_cube_forward(wqa, dev)
         log(f"96^3 deformed cube forward: {cube96}")
+        cube96_rows = deformed_cube_forward(wqa, dev, layout="rows")
+        log(f"96^3 deformed cube forward, samples by row: {cube96_rows}")
+        rows_layout = row_layout(wqa, dev, args)
+        log(f"row layout: {rows_layout}")
 
     probe = hbm_probe(dev)
     log(f"hbm probe: {probe}")
@@ -626,6 +677,8 @@ def main():
         "pattern_probes": patterns,
         "matrix_free": mfree,
         "forward_96cubed_deformed_cube": cube96,
+        "forward_96cubed_deformed_cube_rows": cube96_rows,
+        "sample_layout_rows": rows_layout,
         "rule_counts": counts.report(P, NEL),
     }
     if r64 is not None:
