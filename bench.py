@@ -14,11 +14,14 @@ pattern probes of libwqa_probes.so (the ceiling of each kernel's byte pattern) a
 plain streaming, and (cpu_baseline) the FP64 CPU oracle timed on a row sample, which
 also states the error of every GPU result on that sample.
 
-Grid buffers (coefficient samples and gradients) are allocated with their last-direction
-lines padded to a multiple of 32 values (wqa_set_grid_pitch), so that every line starts
-on a 128-byte boundary; the padding is never read or written.
+Sample buffers (coefficient samples and gradients) are stored row by row by default
+(wqa_set_sample_layout: each row's (p+1)^3 points as one block; the same values and
+bytes as the grid, and bit-identical results).  --layout grid puts them on the grid with
+the last-direction lines padded to a multiple of 32 values (wqa_set_grid_pitch), so that
+every line starts on a 128-byte boundary; the padding is never read or written.  The
+other layout's forward and adjoint are timed beside the headline.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--layout rows|grid]
 """
 import argparse
 import hashlib
@@ -61,6 +64,8 @@ def parse():
     ap.add_argument("--cube96-only", action="store_true",
                     help="run only the 96^3 deformed-cube forward and print its figures (profiler runs)")
     ap.add_argument("--no-probes", action="store_true", help="leave out the memory-pattern probes")
+    ap.add_argument("--layout", choices=("rows", "grid"), default="rows",
+                    help="sample buffers stored row by row (default) or on the grid with padded lines")
     ap.add_argument("--probe-sweep", type=int, default=0, metavar="N_EL",
                     help="only time the memory-pattern probe variants on the N_EL^3 cubic space (the layout "
                          "experiments behind the kernels' design) and print them")
@@ -88,13 +93,26 @@ def padded(sp, dense):
     return buf
 
 
+def use_layout(sp, layout):
+    """Samples stored row by row, or on the grid with lines padded to LINE_ALIGN values."""
+    if layout == "rows":
+        sp.set_sample_layout("rows")
+    else:
+        sp.set_grid_pitch(padded_pitch(sp))
+
+
+def place(sp, dense):
+    """A dense grid-shaped field in the space's sample layout."""
+    return sp.rows_from_grid(dense) if sp.sample_layout == "rows" else padded(sp, dense)
+
+
 def make_inputs(sp, dtype):
     dev = sp.device
     fields = []
     for field in ["c", 0, 1, 2]:
         fid = 0 if field == "c" else field + 1
         dense = si.fourier_grid(sp.grid_axes(field), si.fourier_modes(SEED_FAMILY, fid, 3), dtype, dev)
-        fields.append(padded(sp, dense))
+        fields.append(place(sp, dense))
         del dense
     gM = si.upstream_gradient(NEL, P, 1000 * SEED_FAMILY + 1, dtype, dev)
     gK = si.upstream_gradient(NEL, P, 1000 * SEED_FAMILY + 2, dtype, dev)
@@ -128,19 +146,22 @@ def hbm_probe(dev, gib=2, reps=5):
 
 class Sample:
     """Rows whose results the oracle checks: a contiguous block in the middle of the row
-    range, with the grid offsets of their points."""
+    range, with the buffer offsets of their points (in the space's sample layout)."""
 
     def __init__(self, sp, n_rows):
         n = [e + P for e in NEL]
         start = sp.n_rows // 2 - n_rows // 2
         self.rows = np.arange(start, start + n_rows, dtype=np.int64)
         Q = P + 1
-        idx = [self.rows // (n[1] * n[2]), (self.rows // n[2]) % n[1], self.rows % n[2]]
-        qs = np.array(np.unravel_index(np.arange(Q ** 3), [Q] * 3))
-        off = np.zeros((self.rows.size, Q ** 3), dtype=np.int64)
-        dims = list(sp.buffer_shape)            # the last direction's lines may be padded
-        for k in range(3):
-            off = off * dims[k] + idx[k][:, None] * Q + qs[k][None, :]
+        if sp.sample_layout == "rows":
+            off = self.rows[:, None] * Q ** 3 + np.arange(Q ** 3)[None, :]
+        else:
+            idx = [self.rows // (n[1] * n[2]), (self.rows // n[2]) % n[1], self.rows % n[2]]
+            qs = np.array(np.unravel_index(np.arange(Q ** 3), [Q] * 3))
+            off = np.zeros((self.rows.size, Q ** 3), dtype=np.int64)
+            dims = list(sp.buffer_shape)            # the last direction's lines may be padded
+            for k in range(3):
+                off = off * dims[k] + idx[k][:, None] * Q + qs[k][None, :]
         self.ridx = torch.from_numpy(self.rows).to(sp.device)
         self.pidx = torch.from_numpy(off.reshape(-1)).to(sp.device)
 
@@ -274,11 +295,10 @@ def deformed_cube_forward(wqa, dev, reps=20, layout="grid"):
     return out
 
 
-def row_layout(wqa, dev, args, reps=10):
-    """The headline space's forward and adjoint with the samples stored row by row
-    (wqa_set_sample_layout): FP32 (headline final pass) and FP64, event-timed, mean per
-    call, with the fraction of the 8 TB/s HBM peak (the algorithmic bytes do not depend
-    on the layout)."""
+def other_layout(wqa, dev, args, layout, reps=10):
+    """The headline space's forward and adjoint in another sample layout: FP32 (headline
+    final pass) and FP64, event-timed, mean per call, with the fraction of the 8 TB/s HBM
+    peak (the algorithmic bytes do not depend on the layout)."""
     def timed(fn):
         fn()
         e0, e1 = ev(), ev()
@@ -290,12 +310,12 @@ def row_layout(wqa, dev, args, reps=10):
         return e0.elapsed_time(e1) / reps
 
     sp = wqa.Space(3, P, NEL, device=dev)
-    sp.set_sample_layout("rows")
-    out = {}
+    use_layout(sp, layout)
+    out = {"sample_layout": layout}
     for dtype in ((torch.float32,) if args.skip_fp64 else (torch.float32, torch.float64)):
         b = 4 if dtype == torch.float32 else 8
         nbytes = sp.n_rows * (2 * sp.slots_per_row + 4 * sp.points_per_row) * b
-        f = [sp.rows_from_grid(si.fourier_grid(sp.grid_axes(fl), si.fourier_modes(SEED_FAMILY, fid, 3), dtype, dev))
+        f = [place(sp, si.fourier_grid(sp.grid_axes(fl), si.fourier_modes(SEED_FAMILY, fid, 3), dtype, dev))
              for fid, fl in enumerate(["c", 0, 1, 2])]
         M = torch.empty(sp.n_rows, sp.slots_per_row, dtype=dtype, device=dev)
         K = torch.empty_like(M)
@@ -326,7 +346,13 @@ def pattern_probes(sp, fields, M, K, gM, gK, grads, reps=10):
                                  ctypes.POINTER(ctypes.c_int64), vp, vp, ctypes.POINTER(vp), vp]
     stream = lambda: vp(torch.cuda.current_stream().cuda_stream)
     ne = (ctypes.c_int64 * 3)(*NEL)
-    pad = 256 if sp.buffer_shape[-1] == padded_pitch(sp) != sp.grid_shape[-1] else 0
+    # the probe variant of each kernel's layout and order: forward tiles in runs of 8 per
+    # XCD; the FP32 adjoint's tiles in runs of 8 per XCD (order bits 128)
+    if sp.sample_layout == "rows":
+        fwd_code, adj_layout = 3 | 512, 512 | 128
+    else:
+        pad = 256 if sp.buffer_shape[-1] == padded_pitch(sp) != sp.grid_shape[-1] else 0
+        fwd_code, adj_layout = 3 | pad, pad | 128
 
     def timed(fn):
         rc = fn()
@@ -342,9 +368,9 @@ def pattern_probes(sp, fields, M, K, gM, gK, grads, reps=10):
     out = {}
     fp = (vp * 4)(*[t.data_ptr() for t in fields])
     gp = (vp * 4)(*[t.data_ptr() for t in grads])
-    out["forward_pattern_ms"] = timed(lambda: lib.wqap_forward(3 | pad, 0, P, ne, fp, vp(M.data_ptr()),
+    out["forward_pattern_ms"] = timed(lambda: lib.wqap_forward(fwd_code, 0, P, ne, fp, vp(M.data_ptr()),
                                                                vp(K.data_ptr()), stream()))
-    out["adjoint_pattern_ms"] = timed(lambda: lib.wqap_adjoint(3, pad, 0, P, ne, vp(gM.data_ptr()),
+    out["adjoint_pattern_ms"] = timed(lambda: lib.wqap_adjoint(3, adj_layout, 0, P, ne, vp(gM.data_ptr()),
                                                                vp(gK.data_ptr()), gp, stream()))
     nb = 2 << 30
     a = torch.empty(nb // 4, dtype=torch.float32, device=sp.device)
@@ -462,8 +488,8 @@ def make_inputs_fields(sp, dtype):
     fields = []
     for field in ["c", 0, 1, 2]:
         fid = 0 if field == "c" else field + 1
-        fields.append(padded(sp, si.fourier_grid(sp.grid_axes(field), si.fourier_modes(SEED_FAMILY, fid, 3), dtype,
-                                                  sp.device)))
+        fields.append(place(sp, si.fourier_grid(sp.grid_axes(field), si.fourier_modes(SEED_FAMILY, fid, 3), dtype,
+                                                 sp.device)))
     return fields, None, None
 
 
@@ -504,9 +530,9 @@ def per_entry(got, want, scale):
     return float((np.abs(got - want) / np.where(eff == 0, 1, eff)).max())
 
 
-def traffic_for(kernel):
+def traffic_for(kernel, layout):
     """HBM bytes per launch of `kernel` from the committed counter summary, provided it
-    was taken on the current kernel source (else None)."""
+    was taken on the current kernel source and in the same sample layout (else None)."""
     try:
         with open(TRAFFIC_FILE) as f:
             data = json.load(f)
@@ -515,7 +541,7 @@ def traffic_for(kernel):
     except (OSError, ValueError):
         return None
     entry = data.get("kernels", {}).get(kernel)
-    if not entry or data.get("kernel_source_sha256") != src:
+    if not entry or data.get("kernel_source_sha256") != src or data.get("sample_layout", "grid") != layout:
         return None
     return entry["fetch_bytes"] + entry["write_bytes"]
 
@@ -547,7 +573,7 @@ def main():
         del src, dst
         log("calibration copy: 3 x 1 GiB read + 1 GiB written")
     sp = wqa.Space(3, P, NEL, device=dev)
-    sp.set_grid_pitch(padded_pitch(sp))
+    use_layout(sp, args.layout)
     nnz_mat = sp.n_rows * sp.slots_per_row
     nnz_step = 4 * nnz_mat
     log(f"space: {sp.n_rows} rows x {sp.slots_per_row} slots, grid {sp.grid_shape}, buffers {sp.buffer_shape}")
@@ -606,7 +632,8 @@ def main():
         del r64["out"], f64, gM64, gK64
         torch.cuda.empty_cache()
 
-    mfree, cube96, cube96_rows, rows_layout = None, None, None, None
+    mfree, cube96, cube96_rows, alt = None, None, None, None
+    alt_layout = "grid" if args.layout == "rows" else "rows"
     if not args.headline_only:
         mfree = matrix_free(sp, args)
         log(f"matrix-free: {mfree}")
@@ -614,8 +641,8 @@ def main():
         log(f"96^3 deformed cube forward: {cube96}")
         cube96_rows = deformed_cube_forward(wqa, dev, layout="rows")
         log(f"96^3 deformed cube forward, samples by row: {cube96_rows}")
-        rows_layout = row_layout(wqa, dev, args)
-        log(f"row layout: {rows_layout}")
+        alt = other_layout(wqa, dev, args, alt_layout)
+        log(f"{alt_layout} layout: {alt}")
 
     probe = hbm_probe(dev)
     log(f"hbm probe: {probe}")
@@ -632,7 +659,7 @@ def main():
 
     def roof(ms, kernel, pattern_ms):
         achieved = alg_bytes / (ms * 1e-3) / 1e9
-        traffic = traffic_for(kernel)
+        traffic = traffic_for(kernel, args.layout)
         wb = write_bytes[kernel]
         out = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": alg_bytes,
@@ -664,7 +691,9 @@ def main():
                                "directional pass accumulated in FP64 (Dot2-compensated FP32 pass reported beside it)",
                    "final_pass": "f64_accumulate",
                    "rows": sp.n_rows, "slots_per_row": sp.slots_per_row, "nnz_per_step": nnz_step,
-                   "grid_pitch": sp.buffer_shape[-1], "parallelism": "single GPU"},
+                   "sample_layout": args.layout,
+                   "grid_pitch": sp.buffer_shape[-1] if args.layout == "grid" else None,
+                   "parallelism": "single GPU"},
         "forward_ms": r32["fwd_ms"],
         "adjoint_ms": r32["adj_ms"],
         "kernel_ms_per_call": r32["stats"],
@@ -678,7 +707,7 @@ def main():
         "matrix_free": mfree,
         "forward_96cubed_deformed_cube": cube96,
         "forward_96cubed_deformed_cube_rows": cube96_rows,
-        "sample_layout_rows": rows_layout,
+        f"sample_layout_{alt_layout}": alt,
         "rule_counts": counts.report(P, NEL),
     }
     if r64 is not None:

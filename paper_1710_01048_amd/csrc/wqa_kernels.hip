@@ -731,9 +731,10 @@ struct Adjoint {
     static_assert(RING >= 2 && RING <= 4 && (RING - 1) * NPF < 64, "ring depth");
     static constexpr bool LIMIT = sizeof(T) == 8;
     static constexpr int NT = LB ? P + 1 : S;            // last-direction table entries per lane
-    // Samples stored row by row: the tile's gradients of a field leave through the ring
-    // buffer of the run's last slab, free from its contraction until the next matrix's first
-    // acquire refills it, CH rows at a time.
+    // Samples stored row by row: the tile's gradients leave through LDS staging in the
+    // ring -- before the stream's last slab through the buffer of the run's last slab (free
+    // from its contraction until the next matrix's first acquire refills it), CH rows of
+    // one field at a time; after it through the whole ring.
     static constexpr int QD = (D == 3) ? Q * Q * Q : Q * Q;
     static constexpr int CH = (SLOT * 4 / (int)sizeof(T)) / QD < R ? (SLOT * 4 / (int)sizeof(T)) / QD : R;
     static_assert(CH >= 1, "a ring buffer holds at least one row of gradients");
@@ -890,52 +891,76 @@ struct Adjoint {
         }
     }
 
-    // Samples stored row by row: per field, the values val(m, q1, q2) of the lane's point
-    // column go to the staging buffer -- value w = (q1 Q + q2) Q + ql of row r at
-    // r QD + (w ^ swz(r)), a swizzle that spreads one store instruction over the banks --
-    // and the tile's block of rows_here x QD values (CH rows at a time) leaves with 16-byte
-    // stores, consecutive lanes at consecutive addresses.
     // a slab result as the final pass takes it (see opaque)
     static __device__ __forceinline__ T fin(T z) {
         if constexpr (FINAL == 2 && sizeof(T) == 4) return opaque(z);
         else return z;
     }
 
+    // Samples stored row by row: the values val(m, q1, q2) of each lane's point column go
+    // to a staging buffer in LDS -- value w = (q1 Q + q2) Q + ql of row r at
+    // r QD + (w ^ swz(r)), a swizzle that spreads one store instruction over the banks --
+    // and the tile's block of rows_here x QD values of each field leaves with 16-byte
+    // stores, consecutive lanes at consecutive addresses.
     static __device__ __forceinline__ int swz(int r) {
         constexpr int MASK = (QD & (QD - 1)) == 0 && QD >= 16 ? (QD / 4 < 16 ? QD / 4 : 16) - 1 : 0;
         return (r & MASK) << 2;
     }
 
-    template <int NSET, class F>
-    __device__ __forceinline__ void store_rows(int pos_last, F val, T *const (&out)[NSET]) const {
+    // NF fields and CHX rows per round: the lanes of those rows put their values in buf,
+    // then the wave stores each field's CHX rows as one contiguous block.
+    template <int NSET, int NF, int CHX, class F>
+    __device__ __forceinline__ void stage_out(T *buf, F val, T *const (&out)[NSET]) const {
         constexpr int VEC = (QD * (int)sizeof(T)) % 16 == 0 ? 16 / (int)sizeof(T) : 1;
         using V = T __attribute__((ext_vector_type(VEC)));
-        T *stg = reinterpret_cast<T *>(ring + (pos_last % RING) * SLOT);
 #pragma unroll
-        for (int m = 0; m < NSET; ++m) {
+        for (int m0 = 0; m0 < NSET; m0 += NF) {
 #pragma unroll
-            for (int c0 = 0; c0 < R; c0 += CH) {
+            for (int c0 = 0; c0 < R; c0 += CHX) {
                 const int rr = t.r - c0;
-                if (t.active && rr >= 0 && rr < CH) {
+                if (t.active && rr >= 0 && rr < CHX) {
 #pragma unroll
-                    for (int q1 = 0; q1 < Q; ++q1)
+                    for (int mm = 0; mm < NF && m0 + mm < NSET; ++mm)
 #pragma unroll
-                        for (int q2 = 0; q2 < NQ2; ++q2)
-                            stg[rr * QD + (((q1 * NQ2 + q2) * Q + ql) ^ swz(rr))] = val(m, q1, q2);
+                        for (int q1 = 0; q1 < Q; ++q1)
+#pragma unroll
+                            for (int q2 = 0; q2 < NQ2; ++q2)
+                                buf[(mm * CHX + rr) * QD + (((q1 * NQ2 + q2) * Q + ql) ^ swz(rr))] = val(m0 + mm, q1, q2);
                 }
                 wave_lds_sync();
-                const int nr = t.rows_here - c0 < CH ? t.rows_here - c0 : CH;
+                const int nr = t.rows_here - c0 < CHX ? t.rows_here - c0 : CHX;
                 if (nr > 0) {
-                    T *dst = out[m] + (t.row0 + c0) * QD;
                     const int nv = nr * QD / VEC;
-                    for (int k = lane; k < nv; k += 64) {
-                        const int e = k * VEC, r = e / QD, w = e - r * QD;
-                        *reinterpret_cast<V *>(dst + e) = *reinterpret_cast<const V *>(stg + r * QD + (w ^ swz(r)));
+#pragma unroll
+                    for (int mm = 0; mm < NF && m0 + mm < NSET; ++mm) {
+                        T *dst = out[m0 + mm] + (t.row0 + c0) * QD;
+                        const T *src = buf + mm * CHX * QD;
+                        for (int k = lane; k < nv; k += 64) {
+                            const int e = k * VEC, r = e / QD, w = e - r * QD;
+                            *reinterpret_cast<V *>(dst + e) = *reinterpret_cast<const V *>(src + r * QD + (w ^ swz(r)));
+                        }
                     }
                 }
                 wave_lds_sync();
             }
         }
+    }
+
+    // The run's gradients, val(m, q1, q2) for the lane's point column.  Before the stream's
+    // last slab only the ring buffer of the run's last slab is free (one field and CH rows
+    // per round); after it the whole ring is, and every field goes through it together,
+    // CHA rows per round (FP32 cubic: the whole tile in one round).
+    template <int NSET, class F>
+    __device__ __forceinline__ void store_rows(int pos_last, F val, T *const (&out)[NSET]) const {
+        constexpr int CAP = RING * SLOT * 4 / (int)sizeof(T) / (NSET * QD);
+        constexpr int CHA = CAP < R ? CAP : R;
+        if constexpr (CHA >= 1) {
+            if (pos_last == n_tot - 1) {
+                stage_out<NSET, NSET, CHA>(reinterpret_cast<T *>(ring), val, out);
+                return;
+            }
+        }
+        stage_out<NSET, 1, CH>(reinterpret_cast<T *>(ring + (pos_last % RING) * SLOT), val, out);
     }
 
     // Final pass of output (m, q1, q2): sum over s1 of the first-direction table entry times

@@ -1,5 +1,6 @@
 """Host-side parts of bench.py (no GPU): the one-GPU guard and the lookup of the
-committed HBM counters, which must refuse figures taken on another kernel source."""
+committed HBM counters, which must refuse figures taken on another kernel source or in
+another sample layout."""
 import hashlib
 import json
 import os
@@ -27,6 +28,8 @@ def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     with open(bench.KERNEL_SRC, "rb") as f:
         current = hashlib.sha256(f.read()).hexdigest() == data["kernel_source_sha256"]
     kernels = data["kernels"]
+    layout = data.get("sample_layout", "grid")
+    other_layout = "grid" if layout == "rows" else "rows"
     assert set(kernels) >= {"forward_fp32_mk", "adjoint_fp32_mk"}
     for name, entry in kernels.items():
         want = entry["fetch_bytes"] + entry["write_bytes"]
@@ -34,10 +37,12 @@ def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
         # other workload would not
         assert 0.7 < want / 16318254696 < 1.3, name
         # taken on this kernel source: reported; else (kernels changed since): null
-        assert bench.traffic_for(name) == (pytest.approx(want) if current else None)
-    assert bench.traffic_for("no_such_kernel") is None
+        assert bench.traffic_for(name, layout) == (pytest.approx(want) if current else None)
+        # figures of one layout never stand for the other
+        assert bench.traffic_for(name, other_layout) is None
+    assert bench.traffic_for("no_such_kernel", layout) is None
     # the same summary against a different kernel source gives no figure at all
     other = tmp_path / "kernels.hip"
     other.write_text("// another kernel source\n")
     monkeypatch.setattr(bench, "KERNEL_SRC", str(other))
-    assert bench.traffic_for("forward_fp32_mk") is None
+    assert bench.traffic_for("forward_fp32_mk", layout) is None
