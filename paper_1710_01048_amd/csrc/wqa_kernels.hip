@@ -583,7 +583,10 @@ __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     __shared__ __align__(16) T stage[WPB][OUT > IN ? OUT : IN];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t task = task0 + (int64_t)block_grouped<8>() * WPB + wave;
+    // runs of 8 tiles per XCD on the grid (neighbouring tiles share the cache lines of
+    // their sample runs); samples stored row by row share none, and runs of 128 tiles per
+    // XCD measured 2-3% faster there (160^3 and 96^3)
+    const int64_t task = task0 + (int64_t)(sp.rows ? block_grouped<128>() : block_grouped<8>()) * WPB + wave;
     if (task >= n_tasks) return;                   // whole wave leaves; no block barriers below
     const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, S, lane, kLinesAll);
     if (tile_banded<D, P>(sp, t))
@@ -803,11 +806,11 @@ struct Adjoint {
     }
 
     // Makes slab `pos` of the stream readable: refills the buffer read last (its reads are
-    // complete) with slab pos + RING - 1, waits for slab pos and zeroes its slots outside
-    // the space, then waits for every load of the wave.  The last wait keeps no slab in
-    // flight while this one is contracted: in same-process A/B runs at 160^3 that was 6%
-    // faster in FP32 (3% in FP64) than waiting for slab pos alone, and 2% faster than
-    // waiting for everything before issuing the next slab.  Every lane takes part.
+    // complete) with slab pos + RING - 1, waits for slab pos (vector memory operations
+    // complete in issue order, so a count of outstanding loads names the slabs still in
+    // flight) and zeroes its slots outside the space; the later slabs stay in flight while
+    // this one is contracted.  (Waiting for every load instead measured 6% slower in FP32
+    // at 160^3 and 10% at 96^3, the same in FP64.)  Every lane takes part.
     __device__ __forceinline__ const T *acquire(int pos) const {
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         if (pos + RING - 1 < n_tot) issue(pos + RING - 1);
@@ -820,7 +823,6 @@ struct Adjoint {
                 if (!((valid >> k) & 1u) && (64 * (k + 1) <= NE || lane + 64 * k < NE)) slot[64 * k + lane] = 0u;
         }
         wave_lds_sync();
-        wait_vm<0>();
         return reinterpret_cast<const T *>(slot);
     }
 
