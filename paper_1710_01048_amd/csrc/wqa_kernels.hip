@@ -17,13 +17,11 @@
 //   * Adjoint: lane (r, q_d) owns one node column of row r.  The upstream gradients
 //     stream through a ring of s_1 slabs in LDS filled by direct global-to-LDS loads
 //     (slots outside the space zeroed), are contracted over s_d, s_{d-1}, ..., and the
-//     gradient of every sample is stored directly (consecutive lanes = consecutive grid
-//     points).
-//   * The adjoint launches one kernel over the "interior" lines (every leading index at
-//     least P from both ends, so the leading tables are banded) and one over the rest,
-//     so that each kernel holds only the registers of its own code path (the interior
-//     one gains occupancy).  The forward's occupancy is set by its LDS, so it runs all
-//     lines in one launch and picks the code path per wave.
+//     gradient of every sample is stored: on the grid directly (consecutive lanes =
+//     consecutive grid points), stored row by row through LDS as whole blocks.
+//   * Each kernel runs every line in one launch and picks the code path per wave: the
+//     banded loops where the tile's leading indices are interior (leading tables banded),
+//     the full loops elsewhere.
 //   * Stiffness: term k uses the stiffness table in direction k and mass tables
 //     elsewhere.  Forward terms with the mass table in direction 1 share the final
 //     pass; adjoint terms with the mass table in direction d share the first pass.
@@ -210,45 +208,14 @@ struct Tile {
     bool in_tile, active;
 };
 
-// Sets of lines a launch covers: all of them, the interior ones (every leading index at
-// least P from both ends: banded tables in every leading direction) or the others.
-enum LineSet { kLinesAll = 0, kLinesInterior = 1, kLinesBoundary = 2 };
-
-// Line l of a set, enumerated in row order, as its index among all lines
-// ((i_1 n_2) + i_2 for d = 3, i_1 for d = 2).  ls is a compile-time constant in every
-// kernel but the adjoint's non-banded one.
-template <int D, int P>
-__device__ __forceinline__ int64_t line_of(const DevSpace &sp, int64_t l, int ls) {
-    if (ls == kLinesAll) return l;
-    const int64_t n0 = sp.n[0];
-    if constexpr (D == 2) {
-        if (ls == kLinesInterior) return P + l;
-        else return l < P ? l : n0 - 2 * P + l;
-    } else {
-        const int64_t n1 = sp.n[1];
-        if (ls == kLinesInterior) {
-            const int64_t w = n1 - 2 * P, a = l / w;
-            return (P + a) * n1 + P + (l - a * w);
-        } else {
-            const int64_t full = 2 * P * n1;            // i_1 among the first or last P
-            if (l < full) {
-                const int64_t a = l / n1;
-                return (a < P ? a : n0 - 2 * P + a) * n1 + (l - a * n1);
-            }
-            const int64_t r = l - full, a = r / (2 * P), b = r - a * (2 * P);
-            return (P + a) * n1 + (b < P ? b : n1 - 2 * P + b);
-        }
-    }
-}
-
 template <int D, int P>
 __device__ __forceinline__ Tile make_tile(const DevSpace &sp, int64_t task, int tiles_per_line, int R,
-                                          int lanes_per_row, int lane, int ls) {
+                                          int lanes_per_row, int lane) {
     Tile t;
-    // 32-bit divisions while the operands fit (64-bit ones take dozens of instructions)
-    const int64_t l = task < INT32_MAX ? (int64_t)((uint32_t)task / (uint32_t)tiles_per_line) : task / tiles_per_line;
-    const int tile = (int)(task - l * tiles_per_line);
-    const int64_t line = line_of<D, P>(sp, l, ls);
+    // line (i_1 n_2) + i_2 (d = 3) or i_1 (d = 2), then the tile within it; 32-bit divisions
+    // while the operands fit (64-bit ones take dozens of instructions)
+    const int64_t line = task < INT32_MAX ? (int64_t)((uint32_t)task / (uint32_t)tiles_per_line) : task / tiles_per_line;
+    const int tile = (int)(task - line * tiles_per_line);
     t.nl = sp.n[D - 1];
     if constexpr (D == 3) {
         t.i1 = (line < INT32_MAX && sp.n[1] < INT32_MAX) ? (int64_t)((uint32_t)line / (uint32_t)sp.n[1])
@@ -588,7 +555,7 @@ __global__ __launch_bounds__(64 * WPB) void forward_kernel(
     // XCD measured 2-3% faster there (160^3 and 96^3)
     const int64_t task = task0 + (int64_t)(sp.rows ? block_grouped<128>() : block_grouped<8>()) * WPB + wave;
     if (task >= n_tasks) return;                   // whole wave leaves; no block barriers below
-    const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, S, lane, kLinesAll);
+    const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, S, lane);
     if (tile_banded<D, P>(sp, t))
         forward_body<T, P, D, WHAT, FINAL, true, R>(sp, tb, t, stage[wave], lane, cf, a0, a1, a2, Mo, Ko);
     else
@@ -1176,14 +1143,17 @@ __device__ __forceinline__ void adjoint_body(const DevSpace &sp, const DevTabs &
     }
 }
 
-// INTERIOR: the banded kernel over the interior lines.  Otherwise the full loops over
-// the lines of line_set (the boundary lines, or every line when some leading direction's
-// tables are not banded).  ROWS: gradients stored row by row.
-template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int RING, bool INTERIOR, bool ROWS>
+// Every tile of every line; BANDED: every leading direction's tables are banded, and each
+// tile whose leading indices are interior takes the banded loops (the others the full
+// loops, which every tile takes when BANDED is false).  One launch for both kinds of tile
+// measured faster than a launch per kind (FP32: 2% at 160^3, 4% at 96^3; FP64: 1-12% at
+// 160^3), now that both code paths fit the same registers.  ROWS: gradients stored row by
+// row.
+template <typename T, int P, int D, int WHAT, int FINAL, int WPB, int RING, bool BANDED, bool ROWS>
 __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
     DevSpace sp, DevTabs tb, const T *__restrict__ gM, const T *__restrict__ gK,
     T *__restrict__ dc, T *__restrict__ da0, T *__restrict__ da1, T *__restrict__ da2,
-    int64_t task0, int64_t n_tasks, int tiles_per_line, int line_set) {
+    int64_t task0, int64_t n_tasks, int tiles_per_line) {
     constexpr int Q = P + 1;
     constexpr int R = 64 / Q;                      // rows per wave tile
     using A = Adjoint<T, P, D, FINAL, false, WPB, R, RING, false, ROWS>;
@@ -1195,16 +1165,23 @@ __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
     // dispatch order)
     const int64_t task = task0 + (int64_t)(sizeof(T) == 4 ? block_grouped<8>() : block_chunked()) * WPB + wave;
     if (task >= n_tasks) return;
-    const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, Q, lane, INTERIOR ? (int)kLinesInterior : line_set);
-    // interior kernel: tiles whose rows are all banded in the last direction too take the
-    // short last-direction loops (each tile picks its code path)
-    if (INTERIOR && ((sp.band >> (D - 1)) & 1) && t.t0 >= P && t.t0 + t.rows_here + P <= t.nl)
-        adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING, INTERIOR, ROWS>(sp, tb, t, ring[wave], lane, gM,
-                                                                                 gK, dc, da0, da1, da2);
-    else
-        adjoint_body<T, P, D, WHAT, FINAL, INTERIOR, WPB, R, RING, false, ROWS>(sp, tb, t, ring[wave], lane, gM, gK,
-                                                                              dc, da0, da1, da2);
+    const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, Q, lane);
+    // banded tiles whose rows are all banded in the last direction too take the short
+    // last-direction loops
+    const bool last = ((sp.band >> (D - 1)) & 1) && t.t0 >= P && t.t0 + t.rows_here + P <= t.nl;
+    if (BANDED && tile_banded<D, P>(sp, t)) {
+        if (last)
+            adjoint_body<T, P, D, WHAT, FINAL, true, WPB, R, RING, true, ROWS>(sp, tb, t, ring[wave], lane, gM, gK, dc,
+                                                                            da0, da1, da2);
+        else
+            adjoint_body<T, P, D, WHAT, FINAL, true, WPB, R, RING, false, ROWS>(sp, tb, t, ring[wave], lane, gM, gK, dc,
+                                                                             da0, da1, da2);
+    } else {
+        adjoint_body<T, P, D, WHAT, FINAL, false, WPB, R, RING, false, ROWS>(sp, tb, t, ring[wave], lane, gM, gK, dc,
+                                                                          da0, da1, da2);
+    }
 }
+
 
 // --------------------------------------------------------------------------------------
 // Matrix-free products y = M x, y = K x and the load vector.  Lane (r, q_d) as in the
@@ -1374,7 +1351,7 @@ __global__ __launch_bounds__(64 * kApplyWaves, sizeof(T) == 4 ? 4 : 2) void appl
     const int lane = (int)(threadIdx.x & 63);
     const int64_t task = task0 + (int64_t)blockIdx.x * WPB + wave;
     if (task >= n_tasks) return;
-    const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, Q, lane, kLinesAll);
+    const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, Q, lane);
     if constexpr (!ONES) {
         // The window is S (d = 3: S x S) lines of W consecutive values of x, one per
         // leading-direction column pair (j_1, j_2).  For each s1 the lanes take the S x W
@@ -1427,18 +1404,6 @@ __global__ __launch_bounds__(64 * kApplyWaves, sizeof(T) == 4 ? 4 : 2) void appl
 }
 
 // --- dispatch ----------------------------------------------------------------------------
-// Lines of the interior set and of the boundary set (see line_of).
-template <int D, int P>
-void line_sets(const DevSpace &sp, int64_t &interior, int64_t &boundary) {
-    int64_t all = 1, in = 1;
-    for (int k = 0; k < D - 1; ++k) {
-        all *= sp.n[k];
-        in *= sp.n[k] - 2 * P;
-    }
-    interior = in;
-    boundary = all - in;
-}
-
 // Launches kernel(task0, n_tasks) over [0, tasks) in dispatches of at most max_tasks
 // tasks (a multiple of wpb), so that no grid passes HIP's 32-bit work-item count.
 template <class L>
@@ -1487,45 +1452,32 @@ hipError_t run_adjoint(const DevSpace &sp, const DevTabs &tb, const void *gM, co
     constexpr int RING = sizeof(T) == 4 ? 4 : 3;
     constexpr int WPB = 1;
     const int tiles = (int)((sp.n[D - 1] + R - 1) / R);
-    int64_t lines[2];
-    line_sets<D, P>(sp, lines[0], lines[1]);
-    // every leading direction banded: the banded kernel takes the interior lines and the
-    // other kernel the rest; else the other kernel takes every line
+    int64_t lines = 1;
+    for (int k = 0; k < D - 1; ++k) lines *= sp.n[k];
+    const int64_t tasks = lines * tiles;
     const int lead = (1 << (D - 1)) - 1;
     const bool banded = (sp.band & lead) == lead;
-    if (!banded) {
-        lines[1] += lines[0];
-        lines[0] = 0;
-    }
-    const int other_set = banded ? (int)kLinesBoundary : (int)kLinesAll;
     T *d0 = nullptr, *d1 = nullptr, *d2 = nullptr;
     if (WHAT & kWhatK) {
         d0 = (T *)da[0];
         d1 = (T *)da[1];
         d2 = D == 3 ? (T *)da[2] : nullptr;
     }
-    for (int set = 0; set < 2; ++set) {
-        const int64_t tasks = lines[set] * tiles;
-        if (tasks == 0) continue;
-        const dim3 block(64 * WPB);
-        const hipError_t e = split_launch(tasks, max_tasks, WPB, [&](int64_t t0, dim3 grid) {
-            const int64_t end = t0 + (int64_t)grid.x * WPB < tasks ? t0 + (int64_t)grid.x * WPB : tasks;
-            const int ls = set == 0 ? (int)kLinesInterior : other_set;
-            auto go = [&](auto kernel) {
-                hipLaunchKernelGGL(kernel, grid, block, 0, st, sp, tb, (const T *)gM, (const T *)gK, (T *)dc, d0, d1,
-                                   d2, t0, end, tiles, ls);
-            };
-            if (set == 0) {
-                if (sp.rows) go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, true, true>);
-                else go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, true, false>);
-            } else {
-                if (sp.rows) go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, false, true>);
-                else go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, false, false>);
-            }
-        });
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const dim3 block(64 * WPB);
+    return split_launch(tasks, max_tasks, WPB, [&](int64_t t0, dim3 grid) {
+        const int64_t end = t0 + (int64_t)grid.x * WPB < tasks ? t0 + (int64_t)grid.x * WPB : tasks;
+        auto go = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, grid, block, 0, st, sp, tb, (const T *)gM, (const T *)gK, (T *)dc, d0, d1, d2,
+                               t0, end, tiles);
+        };
+        if (banded) {
+            if (sp.rows) go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, true, true>);
+            else go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, true, false>);
+        } else {
+            if (sp.rows) go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, false, true>);
+            else go(adjoint_kernel<T, P, D, WHAT, FINAL, WPB, RING, false, false>);
+        }
+    });
 }
 
 template <typename T, int P, int D, int WHAT, bool ONES>
