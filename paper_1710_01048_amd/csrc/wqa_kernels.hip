@@ -1359,19 +1359,13 @@ __global__ __launch_bounds__(64 * kApplyWaves, sizeof(T) == 4 ? 4 : 2) void appl
     const int64_t task = task0 + (int64_t)blockIdx.x * WPB + wave;
     if (task >= n_tasks) return;
     const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, Q, lane);
-    // y = M x in FP64: the coefficient samples of the lane's points are loaded first, so that
-    // they are in flight while the window is staged and contracted (17% faster at 160^3; in
-    // FP32 the same made y = M x 30% slower)
+    // y = M x in FP64: the coefficient samples of the lane's points are loaded once the window
+    // is staged, so that they are in flight while it is contracted (0.92 against 1.22 ms at
+    // 160^3; 1.01 ms when loaded before the window, whose loads then waited behind them).  In
+    // FP32 either made y = M x 30% slower: 16 more registers cost two waves per SIMD there.
     constexpr int NQ2 = (D == 3) ? Q : 1;
     constexpr bool PRE = sizeof(T) == 8 && WHAT == kWhatM && !ONES;
     T pre[Q][NQ2];
-    if constexpr (PRE) {
-        const SampleIndex<D, P> at(sp, t, lane - t.r * Q);
-#pragma unroll
-        for (int q1 = 0; q1 < Q; ++q1)
-#pragma unroll
-            for (int q2 = 0; q2 < NQ2; ++q2) pre[q1][q2] = (cf + at.uniform(q1, q2))[at.lo];
-    }
     if constexpr (!ONES) {
         // The window is S (d = 3: S x S) lines of W consecutive values of x, one per
         // leading-direction column pair (j_1, j_2).  For each s1 the lanes take the S x W
@@ -1406,6 +1400,13 @@ __global__ __launch_bounds__(64 * kApplyWaves, sizeof(T) == 4 ? 4 : 2) void appl
             }
         }
         wave_lds_sync();
+    }
+    if constexpr (PRE) {
+        const SampleIndex<D, P> at(sp, t, lane - t.r * Q);
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1)
+#pragma unroll
+            for (int q2 = 0; q2 < NQ2; ++q2) pre[q1][q2] = (cf + at.uniform(q1, q2))[at.lo];
     }
     T v;
     const bool last_banded = ((sp.band >> (D - 1)) & 1) && t.t0 >= P && t.t0 + t.rows_here + P <= t.nl;
