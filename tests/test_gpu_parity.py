@@ -207,16 +207,21 @@ def test_adjoint_3d_cubic_64_cubed(wqa, dtype):
     assert max(errs) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("layout", ["rows", "grid"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_forward_adjoint_160_cubed(wqa, dtype):
+def test_forward_adjoint_160_cubed(wqa, dtype, layout):
     # the benchmark workload at full size, in the launch configuration the benchmark
-    # times (default rules and final pass): 160^3 cubic, Fourier c and a_k, fused forward
-    # then adjoint with G ~ N(0,1) (seeds 5001, 5002); a row sample covering every
-    # boundary class and both ragged tails of the last direction against the oracle
+    # times (default rules and final pass, samples stored row by row; the grid layout
+    # too): 160^3 cubic, Fourier c and a_k, fused forward then adjoint with G ~ N(0,1)
+    # (seeds 5001, 5002); a row sample covering every boundary class and both ragged tails
+    # of the last direction against the oracle
     p, n_el = 3, (160, 160, 160)
     sp = wqa.Space(3, p, n_el)
     recipe = ("fourier", 5)
     f = ph.device_fields(sp, recipe, dtype)
+    if layout == "rows":
+        sp.set_sample_layout("rows")
+        f = [sp.rows_from_grid(v) for v in f]
     M, K = sp.assemble_fused(f[0], f[1:])
     rows = st.sample_rows(list(sp.n_basis), p, 300, seed=5)
     ridx = torch.from_numpy(rows).to(sp.device)
@@ -225,7 +230,11 @@ def test_forward_adjoint_160_cubed(wqa, dtype):
     gM = si.upstream_gradient(n_el, p, 5001, dtype, sp.device)
     gK = si.upstream_gradient(n_el, p, 5002, dtype, sp.device)
     dc, da = sp.adjoint(gM, gK)
-    pts = torch.from_numpy(st.point_offsets(list(sp.n_basis), p, rows).reshape(-1)).to(sp.device)
+    if layout == "rows":
+        offs = rows[:, None] * sp.points_per_row + np.arange(sp.points_per_row)[None, :]
+    else:
+        offs = st.point_offsets(list(sp.n_basis), p, rows)
+    pts = torch.from_numpy(offs.reshape(-1)).to(sp.device)
     grads = [g.reshape(-1)[pts].double().cpu().numpy().reshape(rows.size, -1) for g in [dc] + list(da)]
     gm, gk = gM[ridx].double().cpu().numpy(), gK[ridx].double().cpu().numpy()
     del gM, gK, dc, da
@@ -234,7 +243,7 @@ def test_forward_adjoint_160_cubed(wqa, dtype):
     want, scale = ph.oracle_adjoint(p, n_el, oa.rule_tables(p, n_el), gm, gk, rows)
     eM, eK = st.row_scaled_error(Mg, Mw), st.row_scaled_error(Kg, Kw)
     eg = max(ph.entry_errors(grads, want, scale))
-    print(f"160^3 {dtype}: row-scaled M {eM:.3e} K {eK:.3e}; gradients per entry {eg:.3e}")
+    print(f"160^3 {dtype} {layout}: row-scaled M {eM:.3e} K {eK:.3e}; gradients per entry {eg:.3e}")
     assert eM <= TOL[dtype] and eK <= TOL[dtype] and eg <= TOL[dtype]
 
 
