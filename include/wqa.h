@@ -27,6 +27,10 @@
  *               row (row i owns points (i_k Q + q_k)_k).  a_k lives on the grid that
  *               uses the stiffness-rule nodes in direction k and mass-rule nodes in
  *               the other directions.  wqa_get_rules returns those coordinates.
+ *               Sample buffers (c, a_k, f, dc, da_k) hold a grid in this layout, with
+ *               lines optionally padded (wqa_set_grid_pitch), or the same samples row
+ *               by row, [rows][Q^d] (wqa_set_sample_layout); "[N_1..N_d]" below stands
+ *               for whichever layout is set.
  *
  * Alignment: every device buffer (coefficients, matrices, gradients) must start on a
  * 16-byte boundary (hipMalloc and PyTorch allocations do); WQA_EINVAL otherwise.
