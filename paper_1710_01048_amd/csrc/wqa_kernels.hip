@@ -567,13 +567,14 @@ __global__ __launch_bounds__(64 * WPB) void forward_kernel(
 // The upstream gradients of the tile stream through a ring of RING slab buffers in this
 // wave's LDS: one buffer holds one s1 slab (R rows x S^(d-1) values), filled by direct
 // global-to-LDS loads, so no registers hold the data in flight.  Slab pos + RING - 1 is
-// issued when slab pos is taken up, and every load of the wave is then complete before
-// slab pos is read (see acquire()).  The stream is gM's slabs, then gK's.  Each slab
-// reduces to Z[s1][q2] in registers; the final pass over s1 gives every output directly.
+// issued when slab pos is taken up, then the wave waits for slab pos alone; the later
+// slabs stay in flight while it is contracted (see acquire()).  The stream is gM's slabs,
+// then gK's.  Each slab reduces to Z[s1][q2] in registers; the final pass over s1 gives
+// every output, stored directly on the grid or through LDS as row blocks.
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
 
-// Waits until at most N vector-memory operations of this wave are in flight.  Loads
+// Waits until at most N vector-memory operations of this wave are in flight.  They
 // complete in issue order, so this waits for everything issued before the last N.
 template <int N>
 __device__ __forceinline__ void wait_vm() {
@@ -584,7 +585,8 @@ __device__ __forceinline__ void wait_vm() {
 // S consecutive values of a ring slab (LDS byte address a, aligned to the value size),
 // read in one asm block that also waits for them.  The compiler treats any LDS read as
 // possibly aliasing a pending direct-to-LDS load and puts its own vmcnt(0) wait before it;
-// acquire() places that wait itself, and these reads keep the compiler from adding more.
+// acquire() waits for the slab it hands out, and these reads keep the compiler from
+// adding a wait for the slabs still in flight.
 template <typename T, int S>
 __device__ __forceinline__ void lds_row(uint32_t a, T (&g)[S]) {
     static_assert(S == 5 || S == 7, "rows of 2p+1 values, p = 2 or 3");
