@@ -118,9 +118,9 @@ class Space:
         """Grid buffers (fields and gradients) hold lines of `pitch` values along the last
         direction, the first N_d of them the grid (0: dense).  buffer_shape follows."""
         check(lib.wqa_set_grid_pitch(self._ctx, int(pitch)))
-        last = self.grid_shape[-1] if pitch == 0 else int(pitch)
         self.pitch = int(pitch)
-        self.buffer_shape = self.grid_shape[:-1] + (last,)
+        if self.sample_layout == "grid":        # (only pitch 0 is accepted by row)
+            self.buffer_shape = self.grid_shape[:-1] + (self.pitch or self.grid_shape[-1],)
 
     def set_sample_layout(self, layout):
         """'grid' (the default) or 'rows': every sample buffer (fields, gradients, f)

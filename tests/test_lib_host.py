@@ -233,6 +233,7 @@ def test_sample_layout_arguments(wqa):
     with pytest.raises(wqa.WQAError, match="ESTATE"):
         sp.set_grid_pitch(64)
     sp.set_grid_pitch(0)                                  # the dense grid pitch is always fine
+    assert sp.buffer_shape == (sp.n_rows, 64)             # and leaves the row layout's shape
     sp.set_sample_layout("grid")
     assert sp.buffer_shape == sp.grid_shape
     sp.set_grid_pitch(64)
