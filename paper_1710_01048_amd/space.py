@@ -119,7 +119,7 @@ class Space:
         direction, the first N_d of them the grid (0: dense).  buffer_shape follows."""
         check(lib.wqa_set_grid_pitch(self._ctx, int(pitch)))
         self.pitch = int(pitch)
-        if self.sample_layout == "grid":        # (only pitch 0 is accepted by row)
+        if self.sample_layout == "grid":        # by row only pitch 0 is accepted; the shape stays
             self.buffer_shape = self.grid_shape[:-1] + (self.pitch or self.grid_shape[-1],)
 
     def set_sample_layout(self, layout):
