@@ -347,9 +347,10 @@ def pattern_probes(sp, fields, M, K, gM, gK, grads, reps=10):
     stream = lambda: vp(torch.cuda.current_stream().cuda_stream)
     ne = (ctypes.c_int64 * 3)(*NEL)
     # the probe variant of each kernel's layout and order: forward tiles in runs of 8 per
-    # XCD; the FP32 adjoint's tiles in runs of 8 per XCD (order bits 128)
+    # XCD on the grid, of 128 with samples by row; the FP32 adjoint's tiles in runs of 8 per
+    # XCD (order bits 128)
     if sp.sample_layout == "rows":
-        fwd_code, adj_layout = 3 | 512, 512 | 128
+        fwd_code, adj_layout = 3 | 512 | (3 << 4), 512 | 128     # forward: runs of 128 tiles per XCD
     else:
         pad = 256 if sp.buffer_shape[-1] == padded_pitch(sp) != sp.grid_shape[-1] else 0
         fwd_code, adj_layout = 3 | pad, pad | 128
@@ -438,7 +439,7 @@ def probe_sweep(wqa, dev, n_el, reps=10):
                                                                      vp(K.data_ptr()), stream()))
     for name, code in (("ordinary_stores/stores", 2 | 64), ("ordinary_stores/both", 3 | 64),
                        ("M_only/stores", 2 | 128), ("padded_lines/both", 3 | 256), ("row_samples/loads", 1 | 512),
-                       ("row_samples/both", 3 | 512)):
+                       ("row_samples/both", 3 | 512), ("row_samples_xcd_runs_of_128/both", 3 | 512 | (3 << 4))):
         fwd[name] = timed(lambda: lib.wqap_forward(code, 0, P, ne, fp, vp(M.data_ptr()), vp(K.data_ptr()), stream()))
     out["forward_ms"] = fwd
     adj = {}

@@ -70,8 +70,9 @@ int wqap_adjoint(int parts, int layout, int dtype, int p, const int64_t *n_elem,
  * four fields (c, a_1..a_3) the tile owns are loaded (16-byte loads where the runs
  * allow), and the tile's rows of M and K are written as two contiguous ranges with
  * 16-byte stores (nontemporal in FP32).  parts: bits 0-1 as above; bits 4-5 the
- * work-group order (0: the kernel's, runs of 8 consecutive tiles per XCD; 1: each XCD one
- * contiguous share; 2: dispatch order); bits 6-7: 1 ordinary stores in FP32, 2 M only;
+ * work-group order (0: the kernel's on the grid, runs of 8 consecutive tiles per XCD; 1:
+ * each XCD one contiguous share; 2: dispatch order; 3: runs of 128 tiles per XCD, the
+ * kernel's with samples stored row by row); bits 6-7: 1 ordinary stores in FP32, 2 M only;
  * bit 8: fields with grid lines padded to a multiple of 32 values (as for the adjoint);
  * bit 9: fields stored row by row ([rows][(p+1)^3]), each tile's samples of a field one
  * contiguous block loaded with 16-byte loads.

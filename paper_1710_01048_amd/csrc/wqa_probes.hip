@@ -44,6 +44,13 @@ __device__ __forceinline__ uint32_t order_grouped8() {
     return b - b % span + (b % 8) * 8 + (b / 8) % 8;
 }
 
+// runs of 128 consecutive work-groups per XCD (the forward's order with samples by row)
+__device__ __forceinline__ uint32_t order_grouped128() {
+    const uint32_t b = blockIdx.x, span = 1024u, full = gridDim.x / span * span;
+    if (b >= full) return b;
+    return b - b % span + (b % 8) * 128 + (b / 8) % 128;
+}
+
 // 0: each XCD a contiguous share, 1: dispatch order, 2: runs of 8 per XCD
 __device__ __forceinline__ uint32_t order_of(int order) {
     return order == 0 ? order_chunked() : order == 1 ? blockIdx.x : order_grouped8();
@@ -575,7 +582,8 @@ __global__ __launch_bounds__(64) void forward_probe(Grid3 g, const T *__restrict
     using VO = T __attribute__((ext_vector_type(VEC)));
     __shared__ __align__(16) T stage[OUT > IN ? OUT : IN];
     const int lane = threadIdx.x;
-    const int64_t task = ORDER == 0 ? order_grouped8() : ORDER == 1 ? order_chunked() : blockIdx.x;
+    const int64_t task = ORDER == 0 ? order_grouped8() : ORDER == 1 ? order_chunked() : ORDER == 3 ? order_grouped128()
+                                                                                                 : blockIdx.x;
     if (task >= n_tasks) return;
     const int64_t line = task / tiles_per_line;
     const int tile = (int)(task - line * tiles_per_line);
@@ -685,7 +693,7 @@ int forward_order(int parts, const Grid3 &g, const void *const *f, void *M, void
 }
 
 // parts: bits 0-1 as documented; bits 4-5 the work-group order (0: the kernel's runs of 8
-// per XCD, 1: each XCD one contiguous share, 2: dispatch order)
+// per XCD, 1: each XCD one contiguous share, 2: dispatch order, 3: runs of 128 per XCD)
 template <typename T, int P>
 int forward_parts(int parts, const Grid3 &g, const void *const *f, void *M, void *K, hipStream_t st) {
     const int flags = (parts >> 6) & 3;     // 1: ordinary stores, 2: M only
@@ -693,6 +701,7 @@ int forward_parts(int parts, const Grid3 &g, const void *const *f, void *M, void
         case 0: return forward_order<T, P, 0>(parts & 3, g, f, M, K, st, flags);
         case 1: return forward_order<T, P, 1>(parts & 3, g, f, M, K, st, flags);
         case 2: return forward_order<T, P, 2>(parts & 3, g, f, M, K, st, flags);
+        case 3: return forward_order<T, P, 3>(parts & 3, g, f, M, K, st, flags);
         default: return -1;
     }
 }
