@@ -1358,7 +1358,11 @@ __global__ __launch_bounds__(64 * kApplyWaves, sizeof(T) == 4 ? 4 : 2) void appl
     __shared__ __align__(16) T win[WPB][ONES ? 1 : NL * W];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t task = task0 + (int64_t)blockIdx.x * WPB + wave;
+    // XCD-aware order: neighbouring tiles share most of their x windows.  Runs of 8
+    // work-groups per XCD measured 2-5% faster than dispatch order (160^3, FP32 and FP64);
+    // for FP32 y = K x one contiguous share per XCD did better still (1.19 against 1.25 ms)
+    const uint32_t blk = (sizeof(T) == 4 && WHAT == kWhatK && !ONES) ? block_chunked() : block_grouped<8>();
+    const int64_t task = task0 + (int64_t)blk * WPB + wave;
     if (task >= n_tasks) return;
     const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, Q, lane);
     // y = M x in FP64: the coefficient samples of the lane's points are loaded once the window
