@@ -20,19 +20,21 @@ def wqa():
     return mod
 
 
+@pytest.mark.parametrize("layout", ["grid", "rows"])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
-def test_captured_step_replays_bitwise(wqa, dtype):
+def test_captured_step_replays_bitwise(wqa, dtype, layout):
     p, n_el = 3, (9, 10, 21)
     sp = wqa.Space(3, p, n_el)
+    sp.set_sample_layout(layout)                # samples on the grid or stored row by row
     dev = sp.device
     # static buffers of the graph
-    f = [torch.empty(sp.grid_shape, dtype=dtype, device=dev) for _ in range(4)]
+    f = [torch.empty(sp.buffer_shape, dtype=dtype, device=dev) for _ in range(4)]
     gM = torch.empty(sp.n_rows, sp.slots_per_row, dtype=dtype, device=dev)
     gK = torch.empty_like(gM)
     x = torch.empty(sp.n_rows, dtype=dtype, device=dev)
     M = torch.empty_like(gM)
     K = torch.empty_like(gM)
-    dc = torch.empty(sp.grid_shape, dtype=dtype, device=dev)
+    dc = torch.empty(sp.buffer_shape, dtype=dtype, device=dev)
     da = [torch.empty_like(dc) for _ in range(3)]
     y = torch.empty(sp.n_rows, dtype=dtype, device=dev)
 
@@ -43,6 +45,8 @@ def test_captured_step_replays_bitwise(wqa, dtype):
 
     def inputs(seed):
         fs = ph.device_fields(sp, ("random", seed), dtype)
+        if layout == "rows":
+            fs = [sp.rows_from_grid(t) for t in fs]
         g1 = si.upstream_gradient(n_el, p, seed + 1, dtype, dev)
         g2 = si.upstream_gradient(n_el, p, seed + 2, dtype, dev)
         gen = torch.Generator(device=dev)
