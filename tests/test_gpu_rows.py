@@ -121,3 +121,44 @@ def test_layout_switches(wqa):
         sp.assemble_mass(torch.ones(sp.grid_shape, device=sp.device))
     with pytest.raises(ValueError):
         sp.set_sample_layout("columns")
+
+
+def _reverse_interior_nodes(x, w, n, Q, p):
+    xr, wr = np.asarray(x).reshape(n, Q).copy(), np.asarray(w).reshape(n, Q).copy()
+    xr[p:n - p] = xr[p:n - p, ::-1]
+    wr[p:n - p] = wr[p:n - p, ::-1]
+    return xr.reshape(-1), wr.reshape(-1)
+
+
+@pytest.mark.parametrize("setup", ["unbanded_rules", "nonuniform_knots", "split_dispatches"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_rows_layout_other_code_paths(wqa, setup, dtype):
+    """The row layout against the grid, bit for bit, on the kernels' other paths: rules
+    whose nodes are listed in reverse (the band is broken, every tile takes the full
+    loops), graded knots in one direction, and launches split into dispatches of 7 tiles."""
+    d, p, n_el = 3, 3, (5, 6, 19)
+    Q = p + 1
+    breaks = None
+    if setup == "nonuniform_knots":
+        breaks = [None, [(k / n_el[1]) ** 1.4 for k in range(n_el[1] + 1)], None]
+    sp = wqa.Space(d, p, n_el, breaks=breaks)
+    if setup == "unbanded_rules":
+        n0 = n_el[0] + p
+        for kind in (wqa.MASS, wqa.STIFFNESS):
+            x, w = sp.rules(kind, 0)
+            sp.set_rules(kind, 0, *_reverse_interior_nodes(x, w, n0, Q, p))
+    if setup == "split_dispatches":
+        sp.set_dispatch_limit(7)
+    f = [torch.from_numpy(v).to(sp.device, dtype) for v in ph._random_fields(p, n_el, 121)]
+    gM = si.upstream_gradient(n_el, p, 122, dtype, sp.device)
+    gK = si.upstream_gradient(n_el, p, 123, dtype, sp.device)
+    x = torch.randn(sp.n_rows, generator=torch.Generator().manual_seed(124)).to(sp.device, dtype)
+    grid_out, grid_grads = _everything(sp, f, gM, gK, x, dtype)
+    sp.set_sample_layout("rows")
+    rows_out, rows_grads = _everything(sp, [sp.rows_from_grid(v) for v in f], gM, gK, x, dtype)
+    torch.cuda.synchronize()
+    for k, (a, b) in enumerate(zip(grid_out, rows_out)):
+        assert torch.equal(a, b), f"output {k}"
+    for k, (a, b) in enumerate(zip(grid_grads, rows_grads)):
+        assert not torch.isnan(b).any(), f"gradient {k}: values left unwritten"
+        assert torch.equal(a, sp.grid_from_rows(b)), f"gradient {k}"
