@@ -439,7 +439,8 @@ def probe_sweep(wqa, dev, n_el, reps=10):
                                                                      vp(K.data_ptr()), stream()))
     for name, code in (("ordinary_stores/stores", 2 | 64), ("ordinary_stores/both", 3 | 64),
                        ("M_only/stores", 2 | 128), ("padded_lines/both", 3 | 256), ("row_samples/loads", 1 | 512),
-                       ("row_samples/both", 3 | 512), ("row_samples_xcd_runs_of_128/both", 3 | 512 | (3 << 4))):
+                       ("row_samples/both", 3 | 512), ("row_samples_xcd_runs_of_128/both", 3 | 512 | (3 << 4)),
+                       ("whole_output_lines/stores", 2 | 192), ("whole_output_lines_row_samples/both", 3 | 192 | 512)):
         fwd[name] = timed(lambda: lib.wqap_forward(code, 0, P, ne, fp, vp(M.data_ptr()), vp(K.data_ptr()), stream()))
     out["forward_ms"] = fwd
     adj = {}

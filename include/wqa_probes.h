@@ -72,8 +72,9 @@ int wqap_adjoint(int parts, int layout, int dtype, int p, const int64_t *n_elem,
  * 16-byte stores (nontemporal in FP32).  parts: bits 0-1 as above; bits 4-5 the
  * work-group order (0: the kernel's on the grid, runs of 8 consecutive tiles per XCD; 1:
  * each XCD one contiguous share; 2: dispatch order; 3: runs of 128 tiles per XCD, the
- * kernel's with samples stored row by row); bits 6-7: 1 ordinary stores in FP32, 2 M only;
- * bit 8: fields with grid lines padded to a multiple of 32 values (as for the adjoint);
+ * kernel's with samples stored row by row); bits 6-7: 1 ordinary stores in FP32, 2 M only,
+ * 3 every whole 128-byte line the tile's output ranges touch (their end lines shared with
+ * the neighbouring tiles, so each tile's stores start and end on line boundaries); bit 8: fields with grid lines padded to a multiple of 32 values (as for the adjoint);
  * bit 9: fields stored row by row ([rows][(p+1)^3]), each tile's samples of a field one
  * contiguous block loaded with 16-byte loads.
  * fields[4] = c, a_1, a_2, a_3; M is needed even for the loads alone. */

@@ -648,6 +648,25 @@ __global__ __launch_bounds__(64) void forward_probe(Grid3 g, const T *__restrict
         __builtin_amdgcn_wave_barrier();
     }
     if constexpr (PARTS & 2) {
+        if (flags == 3) {
+            // each tile writes the whole 128-byte lines its output range touches (the lines
+            // at its two ends also belong to the neighbouring tiles, which write them too):
+            // the price of partial lines at tile boundaries
+            constexpr int LINE = 128 / (int)sizeof(T);
+            const int64_t total = g.n[0] * g.n[1] * g.n[2] * (int64_t)SD;
+            const int64_t lo = (row0 * SD) / LINE * LINE;
+            int64_t hi = ((row0 + rows_here) * SD + LINE - 1) / LINE * LINE;
+            hi = hi < total ? hi : total;
+            const int nv = (int)((hi - lo) / VEC);
+            for (int mat = 0; mat < 2; ++mat) {
+                T *ob = (mat == 0 ? Mo : Ko) + lo;
+                for (int k = lane; k < nv; k += 64)
+                    __builtin_nontemporal_store(VO{}, reinterpret_cast<VO *>(ob + (int64_t)k * VEC));
+                const int64_t t0v = lo + (int64_t)nv * VEC;
+                if (lane < hi - t0v) (mat == 0 ? Mo : Ko)[t0v + lane] = T(0);
+            }
+            return;
+        }
         const bool NT = sizeof(T) == 4 && !(flags & 1);
         const int nmat = (flags & 2) ? 1 : 2;
         const int n = rows_here * SD;
