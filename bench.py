@@ -63,6 +63,9 @@ def parse():
                     help="leave out the other workloads (matrix-free products, 96^3 forward): profiler runs")
     ap.add_argument("--cube96-only", action="store_true",
                     help="run only the 96^3 deformed-cube forward and print its figures (profiler runs)")
+    ap.add_argument("--products-only", action="store_true",
+                    help="run only the load vector and matrix-free products and print their figures "
+                         "(profiler runs)")
     ap.add_argument("--no-probes", action="store_true", help="leave out the memory-pattern probes")
     ap.add_argument("--layout", choices=("rows", "grid"), default="rows",
                     help="sample buffers stored row by row (default) or on the grid with padded lines")
@@ -215,17 +218,29 @@ def run_steps(sp, fields, gM, gK, steps, warmup):
             "out": (M, K, dc, da)}
 
 
+def product_macs(p, b1, what, b2=4):
+    """Multiply-adds per row of the blocked 3D product kernel on banded rows: the last
+    direction over the block's (b1 + 2p)(b2 + 2p) window pairs (one table for M, mass and
+    stiffness for K), the second direction over b1 + 2p first-direction columns (one
+    table, or three), the first direction and the samples (one term, or three)."""
+    q = p + 1
+    n3, n2, terms = (1, 1, 1) if what == "M" else (2, 3, 3)
+    d3 = n3 * (b1 + 2 * p) * (b2 + 2 * p) * q * (p + 1) / (b1 * b2)
+    d2 = n2 * q * (b1 + 2 * p) * (p + 1) * q / b1
+    return d3 + d2 + terms * q ** 3 * (p + 1) + terms * q ** 3
+
+
 def matrix_free(sp, args):
     """Load vector and matrix-free products y = M x, y = K x on the same workload (FP32
     and FP64): event-timed per call, with algorithmic HBM bytes per row -- the samples of
     the fields read (Q^d each), x and y (one value each; x's band is re-read from cache)
-    -- and the floating-point work the kernel issues per row (its per-lane contraction:
-    S^2 (S + Q) + S Q^2 multiply-adds per term per node column, Q node columns)."""
+    -- and the multiply-adds the products' kernel issues per row (blocks of B1 x 4 x R
+    rows, B1 = 4 in FP32 and 2 in FP64, banded rows), in `product_macs`."""
     out = {}
-    Q, S, rows = P + 1, 2 * P + 1, sp.n_rows
-    macs_term = Q * (S * S * (S + Q) + S * Q * Q + Q * Q)
+    Q, rows = P + 1, sp.n_rows
     for dtype in ((torch.float32,) if args.skip_fp64 else (torch.float32, torch.float64)):
         b = 4 if dtype == torch.float32 else 8
+        macs = {1: product_macs(P, 4 if b == 4 else 2, "M"), 3: product_macs(P, 4 if b == 4 else 2, "K")}
         fields, _, _ = make_inputs_fields(sp, dtype)
         g = torch.Generator(device=sp.device)
         g.manual_seed(5003)
@@ -244,7 +259,7 @@ def matrix_free(sp, args):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / 10
             nbytes = rows * (nf * Q ** 3 + (2 if terms else 1)) * b
-            flops = 2.0 * rows * (macs_term * terms + nf * Q ** 3)
+            flops = 2.0 * rows * (macs[terms] if terms else Q ** 3)
             res[name] = {"ms": ms, "GB_s": nbytes / (ms * 1e-3) / 1e9, "TFLOP_s": flops / (ms * 1e-3) / 1e12,
                          "rows_per_s": rows / (ms * 1e-3)}
         out["fp32" if b == 4 else "fp64"] = res
@@ -440,7 +455,12 @@ def probe_sweep(wqa, dev, n_el, reps=10):
     for name, code in (("ordinary_stores/stores", 2 | 64), ("ordinary_stores/both", 3 | 64),
                        ("M_only/stores", 2 | 128), ("padded_lines/both", 3 | 256), ("row_samples/loads", 1 | 512),
                        ("row_samples/both", 3 | 512), ("row_samples_xcd_runs_of_128/both", 3 | 512 | (3 << 4)),
-                       ("whole_output_lines/stores", 2 | 192), ("whole_output_lines_row_samples/both", 3 | 192 | 512)):
+                       ("whole_output_lines/stores", 2 | 192), ("whole_output_lines_row_samples/both", 3 | 192 | 512),
+                       ("whole_output_lines_row_samples_xcd_runs_of_128/both", 3 | 192 | 512 | (3 << 4)),
+                       ("line_aligned_stores/stores", 2 | 1024),
+                       ("line_aligned_stores_row_samples_xcd_runs_of_128/both", 3 | 512 | (3 << 4) | 1024),
+                       ("stores_of_constants/stores", 2 | 2048),
+                       ("stores_of_constants_row_samples_xcd_runs_of_128/both", 3 | 512 | (3 << 4) | 2048)):
         fwd[name] = timed(lambda: lib.wqap_forward(code, 0, P, ne, fp, vp(M.data_ptr()), vp(K.data_ptr()), stream()))
     out["forward_ms"] = fwd
     adj = {}
@@ -579,6 +599,9 @@ def main():
     nnz_mat = sp.n_rows * sp.slots_per_row
     nnz_step = 4 * nnz_mat
     log(f"space: {sp.n_rows} rows x {sp.slots_per_row} slots, grid {sp.grid_shape}, buffers {sp.buffer_shape}")
+    if args.products_only:
+        print(json.dumps({"matrix_free": matrix_free(sp, args)}), flush=True)
+        return
 
     sample = None
     if not args.no_cpu_baseline:

@@ -248,8 +248,10 @@ wqa_status wqa_assemble_load(wqa_ctx *ctx, wqa_dtype dtype, const void *f, void 
 
 /* Matrix-free product y = M x with the mass matrix of coefficient c (eq:Mass, eq:LinSys):
  * y_i = sum_j M_ij x_j with the same rules, tables and samples as wqa_assemble_mass, but
- * M is never formed: each row contracts the x values of its band with the tables at its
- * own points, multiplies by c there and sums (eq:Decompo).  c as in wqa_assemble_mass;
+ * M is never formed: x is contracted with the tables to every row's own points, direction
+ * by direction (eq:Decompo; in 3D once per block of neighbouring rows, each partial sum
+ * shared by the rows whose bands contain it), multiplied by c there and summed over each
+ * row's points.  Results equal sum_j M_ij x_j up to rounding order.  c as in wqa_assemble_mass;
  * x, y: device [rows] of dtype (x is read, y fully overwritten; they must not overlap).
  * Arithmetic is plain in the dtype (no compensated final pass). */
 wqa_status wqa_apply_mass(wqa_ctx *ctx, wqa_dtype dtype, const void *c, const void *x, void *y,

@@ -74,9 +74,13 @@ int wqap_adjoint(int parts, int layout, int dtype, int p, const int64_t *n_elem,
  * each XCD one contiguous share; 2: dispatch order; 3: runs of 128 tiles per XCD, the
  * kernel's with samples stored row by row); bits 6-7: 1 ordinary stores in FP32, 2 M only,
  * 3 every whole 128-byte line the tile's output ranges touch (their end lines shared with
- * the neighbouring tiles, so each tile's stores start and end on line boundaries); bit 8: fields with grid lines padded to a multiple of 32 values (as for the adjoint);
- * bit 9: fields stored row by row ([rows][(p+1)^3]), each tile's samples of a field one
- * contiguous block loaded with 16-byte loads.
+ * the neighbouring tiles, so each tile's stores start and end on line boundaries; the values
+ * come from LDS as in the kernel); bit 8: fields with grid lines padded to a multiple of 32
+ * values (as for the adjoint); bit 9: fields stored row by row ([rows][(p+1)^3]), each
+ * tile's samples of a field one contiguous block loaded with 16-byte loads; bit 10: the
+ * 16-byte stores of each range start at its first 128-byte boundary (the values before it
+ * take one 4- or 8-byte store per lane), so that each store instruction covers whole lines;
+ * bit 11: the 16-byte stores write constants instead of values read from LDS.
  * fields[4] = c, a_1, a_2, a_3; M is needed even for the loads alone. */
 int wqap_forward(int parts, int dtype, int p, const int64_t *n_elem, const void *const *fields, void *M,
                  void *K, void *hip_stream);

@@ -57,7 +57,8 @@ def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     # the kernels source once per part (forward, products, FP32 and FP64 adjoint), the
-    # host code and the probes: independent compilations, run side by side
+    # blocked 3D products, the host code and the probes: independent compilations, run
+    # side by side
     jobs = []
     k_objs = []
     for part in range(4):
@@ -66,6 +67,10 @@ def build(verbose=False):
         jobs.append([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *HIP_FLAGS, *inc, f"-DWQA_PART={part}",
                      "-Wno-unneeded-internal-declaration", "-Wno-unused-function", "-c",
                      os.path.join(CSRC, "wqa_kernels.hip"), "-o", obj])
+    p_obj = os.path.join(BUILD, "wqa_products.o")
+    k_objs.append(p_obj)
+    jobs.append([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *HIP_FLAGS, *inc, "-c",
+                 os.path.join(CSRC, "wqa_products.hip"), "-o", p_obj])
     h_obj = os.path.join(BUILD, "wqa_host.o")
     jobs.append([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *HIP_FLAGS, *inc, "-c",
                  os.path.join(CSRC, "wqa_host.cpp"), "-o", h_obj])

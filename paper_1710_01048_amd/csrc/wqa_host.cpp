@@ -1137,8 +1137,13 @@ wqa_status apply(wqa_ctx *c, const char *who, wqa_dtype dtype, int what, bool on
     wqa::DevSpace sp;
     wqa::DevTabs tb;
     fill(c, sp, tb, dtype);
-    hipError_t e = wqa::launch_apply((int)dtype, what, ones, sp, tb, cf, a, x, y, (hipStream_t)stream,
-                                     c->max_tasks);
+    // 3D products: the kernel blocked over all three directions; 2D products and the
+    // load vector: the per-row kernel
+    hipError_t e = (c->dim == 3 && !ones)
+                       ? wqa::launch_apply_blocked((int)dtype, what, sp, tb, cf, a, x, y, (hipStream_t)stream,
+                                                   c->max_tasks)
+                       : wqa::launch_apply((int)dtype, what, ones, sp, tb, cf, a, x, y, (hipStream_t)stream,
+                                           c->max_tasks);
     if (e != hipSuccess) return fail(WQA_EHIP, "%s: kernel launch: %s", who, hipGetErrorString(e));
     return ok();
 }

@@ -50,4 +50,10 @@ hipError_t launch_apply(int dtype, int what, bool ones, const DevSpace &sp, cons
                         const void *c, const void *const *a, const void *x, void *y, hipStream_t stream,
                         int64_t max_tasks);
 
+// The same products in 3D (not the load vector), blocked over rows in every direction
+// (wqa_products.hip); what = kWhatM or kWhatK, sp.d = 3.
+hipError_t launch_apply_blocked(int dtype, int what, const DevSpace &sp, const DevTabs &tb, const void *c,
+                                const void *const *a, const void *x, void *y, hipStream_t stream,
+                                int64_t max_tasks);
+
 }  // namespace wqa

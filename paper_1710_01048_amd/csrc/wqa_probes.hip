@@ -648,11 +648,13 @@ __global__ __launch_bounds__(64) void forward_probe(Grid3 g, const T *__restrict
         __builtin_amdgcn_wave_barrier();
     }
     if constexpr (PARTS & 2) {
-        if (flags == 3) {
+        if ((flags & 3) == 3) {
             // each tile writes the whole 128-byte lines its output range touches (the lines
             // at its two ends also belong to the neighbouring tiles, which write them too):
-            // the price of partial lines at tile boundaries
+            // the price of partial lines at tile boundaries; each store takes its value from
+            // LDS, as in the kernel
             constexpr int LINE = 128 / (int)sizeof(T);
+            constexpr int WRAP = R * SD >= 2048 ? 2048 : R * SD >= 1024 ? 1024 : 512;   // within stage
             const int64_t total = g.n[0] * g.n[1] * g.n[2] * (int64_t)SD;
             const int64_t lo = (row0 * SD) / LINE * LINE;
             int64_t hi = ((row0 + rows_here) * SD + LINE - 1) / LINE * LINE;
@@ -661,7 +663,8 @@ __global__ __launch_bounds__(64) void forward_probe(Grid3 g, const T *__restrict
             for (int mat = 0; mat < 2; ++mat) {
                 T *ob = (mat == 0 ? Mo : Ko) + lo;
                 for (int k = lane; k < nv; k += 64)
-                    __builtin_nontemporal_store(VO{}, reinterpret_cast<VO *>(ob + (int64_t)k * VEC));
+                    __builtin_nontemporal_store(*reinterpret_cast<const VO *>(&stage[(k * VEC) & (WRAP - 1)]),
+                                                reinterpret_cast<VO *>(ob + (int64_t)k * VEC));
                 const int64_t t0v = lo + (int64_t)nv * VEC;
                 if (lane < hi - t0v) (mat == 0 ? Mo : Ko)[t0v + lane] = T(0);
             }
@@ -671,7 +674,10 @@ __global__ __launch_bounds__(64) void forward_probe(Grid3 g, const T *__restrict
         const int nmat = (flags & 2) ? 1 : 2;
         const int n = rows_here * SD;
         const int shift = (int)((row0 * SD) & (VEC - 1));
-        const int head = (VEC - shift) & (VEC - 1);
+        // the 16-byte stores start at the first 16-byte (or, flag 4, 128-byte) boundary of
+        // the range; the values before it take one plain store per lane
+        const int A = (flags & 4) ? 128 / (int)sizeof(T) : VEC;
+        const int head = (int)((A - ((row0 * SD) & (A - 1))) & (A - 1));
         for (int mat = 0; mat < nmat; ++mat) {
             T *ob = (mat == 0 ? Mo : Ko) + row0 * SD;
             auto put = [](bool nt, auto v, auto *dst) {
@@ -682,7 +688,8 @@ __global__ __launch_bounds__(64) void forward_probe(Grid3 g, const T *__restrict
             const int nvec = (n - head) / VEC;
             for (int k = lane; k < nvec; k += 64) {
                 const int e = head + k * VEC;
-                put(NT, *reinterpret_cast<const VO *>(&stage[shift + e]), reinterpret_cast<VO *>(ob + e));
+                const VO v = (flags & 8) ? VO{} : *reinterpret_cast<const VO *>(&stage[shift + e]);
+                put(NT, v, reinterpret_cast<VO *>(ob + e));
             }
             const int tail0 = head + nvec * VEC;
             if (lane < n - tail0) put(NT, stage[shift + tail0 + lane], ob + tail0 + lane);
@@ -715,7 +722,9 @@ int forward_order(int parts, const Grid3 &g, const void *const *f, void *M, void
 // per XCD, 1: each XCD one contiguous share, 2: dispatch order, 3: runs of 128 per XCD)
 template <typename T, int P>
 int forward_parts(int parts, const Grid3 &g, const void *const *f, void *M, void *K, hipStream_t st) {
-    const int flags = (parts >> 6) & 3;     // 1: ordinary stores, 2: M only
+    // 1: ordinary stores, 2: M only, 3: whole lines; 4: 16-byte stores from line boundaries;
+    // 8: 16-byte stores of constants
+    const int flags = ((parts >> 6) & 3) | ((parts >> 8) & 12);
     switch ((parts >> 4) & 3) {
         case 0: return forward_order<T, P, 0>(parts & 3, g, f, M, K, st, flags);
         case 1: return forward_order<T, P, 1>(parts & 3, g, f, M, K, st, flags);
@@ -777,7 +786,7 @@ int wqap_forward(int parts, int dtype, int p, const int64_t *n_elem, const void 
     Grid3 g = grid_of(p, n_elem);
     if (parts & 256) g.pitch = (g.N[2] + 31) / 32 * 32;      // fields with padded grid lines
     if (parts & 512) g.rowpts = 1;                           // fields stored row by row
-    parts &= 255;
+    parts &= 255 | 1024 | 2048;
     hipStream_t st = (hipStream_t)stream;
     if (dtype == 0) return p == 2 ? forward_parts<float, 2>(parts, g, fields, M, K, st)
                                   : forward_parts<float, 3>(parts, g, fields, M, K, st);

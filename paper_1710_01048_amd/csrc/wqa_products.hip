@@ -1,0 +1,417 @@
+// Matrix-free products y = M x and y = K x in 3D on gfx950, blocked over rows in all three
+// directions (eq:LinSys with the rules of eq:GaussQuadSys and eq:GaussQuadSysStiff).
+//
+// With each row's weighted rule, sum_j M_ij x_j = sum_q c(x^i_q) prod_k T_k[i_k, q_k, s_k]
+// x_j (j_k = i_k - p + s_k), where T_k[i, q, s] is the weight of node q of row i times
+// the basis function of column i - p + s at that node (the same tables as the assembled
+// matrices).  Node q of row i is grid point g = i Q + q, and every grid point is a node of
+// exactly one row, so the inner sum is one tensor-product map of x to the grid,
+//     u(g) = sum_j E_1[g_1, j_1] E_2[g_2, j_2] E_3[g_3, j_3] x_j,   E_k[i Q + q, i - p + s] = T_k[i, q, s],
+// and y_i is the sum of c u over the row's points.  A per-row contraction (the adjoint's
+// lane mapping, as in the load vector) re-derives the partial sums of x's window for
+// each of the (2p+1)^2 rows around a leading pair of indices; here a work-group takes a
+// block of B1 x B2 x R rows and forms each partial sum once for the whole block:
+//   1. x over the block's window, (B1 + 2p) (B2 + 2p) (R + 2p) values, zero outside the
+//      space, goes to LDS;
+//   2. direction 3: X3[j1, j2, g3] = sum_s E_3[g3, s] x[j1, j2, s] for every window pair
+//      (j1, j2) and each of the block's R Q last-direction points (lane = g3), into LDS;
+//   3. direction 2 (wave w takes second-direction row i2 = b2 + w, node by node):
+//      X23[j1] = sum_s E_2[g2, s] X3[j1, s, g3] in registers;
+//   4. direction 1: u(g1, g2, g3) = sum_s E_1[g1, s] X23[s], times the coefficient sample
+//      of the point, summed over the row's nodes in q1 and q2 in registers and over q3
+//      across the row's Q lanes.
+// Stiffness term k takes the stiffness table in direction k and the mass tables
+// elsewhere: terms 1 and 2 share X3 of the mass table, term 3 has its own (the same LDS
+// buffer, refilled).  Rows at least p from both ends of a direction whose tables are
+// banded (DevSpace::band) take the P + 1 entries s = q .. q + p of each node; the others
+// all S.  The sums equal the per-row ones up to rounding order.
+#include "wqa_internal.h"
+
+#include <algorithm>
+
+namespace wqa {
+namespace {
+
+template <typename T>
+using uptr = const __attribute__((address_space(4))) T *;     // wave-uniform table reads
+
+template <typename T>
+__device__ __forceinline__ uptr<T> utable(const DevTabs &tb, int kind, int dir) {
+    return (uptr<T>)(const T *)tb.t[kind][dir];
+}
+
+constexpr int kBlockWaves = 4;      // B2: the block's rows along direction 2, one per wave
+
+// Work-group order.  The hardware deals work-groups round-robin over the 8 XCDs, each
+// with its own L2; 0 keeps that order, 1 gives each XCD runs of kRun consecutive blocks
+// (the incomplete last run unchanged), 2 one contiguous share of the dispatch per XCD.
+// Consecutive blocks share the cache lines of their x windows and of their sample runs.
+// At 160^3, p = 3: runs of 8 took 0.355 / 0.815 ms (FP32 y = M x / y = K x) and 0.763 /
+// 1.896 ms (FP64), against 0.367 / 0.846 and 0.828 / 1.938 in dispatch order; runs of 2
+// and one share per XCD fell in between.
+constexpr int kOrder = 1;
+constexpr uint32_t kRun = 8;
+
+__device__ __forceinline__ uint32_t block_order() {
+    const uint32_t b = blockIdx.x, nb = gridDim.x;
+    if constexpr (kOrder == 1) {
+        const uint32_t span = 8u * kRun, full = nb / span * span;
+        return b >= full ? b : b - b % span + (b % 8) * kRun + (b / 8) % kRun;
+    } else if constexpr (kOrder == 2) {
+        const uint32_t q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+        return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+    }
+    return b;
+}
+
+template <int P>
+__device__ __forceinline__ bool interior(int band_bit, int64_t i, int64_t n) {
+    return band_bit && i >= P && i < n - P;
+}
+
+template <typename T, int P, int WHAT, int B1>
+struct Block {
+    static constexpr int Q = P + 1, S = 2 * P + 1, R = 64 / Q, B2 = kBlockWaves;
+    static constexpr int W1 = B1 + 2 * P, W2 = B2 + 2 * P, W3 = R + 2 * P;
+    static constexpr int NPAIR = W1 * W2;       // window pairs (j1, j2)
+    static constexpr int NX = NPAIR * W3;       // window values
+
+    const DevSpace &sp;
+    const DevTabs &tb;
+    const T *xw;       // LDS window [W1][W2][W3] (written by stage_window)
+    T *x3;             // LDS [NPAIR][64]
+    int64_t b1, b2, b3;
+    int wave, lane, i3l, q3;
+    int64_t i3c;       // the lane's last-direction row, clamped into the space
+
+    // Step 2: X3 for every window pair, with the direction-3 table of kind `kind`.
+    template <bool BAND>
+    __device__ __forceinline__ void dir3(int kind) const {
+        constexpr int NT = BAND ? P + 1 : S;
+        const T *tr = (const T *)tb.t[kind][2] + (i3c * Q + q3) * S + (BAND ? q3 : 0);
+        T e[NT];
+#pragma unroll
+        for (int s = 0; s < NT; ++s) e[s] = tr[s];
+        const T *xr = xw + i3l + (BAND ? q3 : 0);
+        for (int pr = wave; pr < NPAIR; pr += kBlockWaves) {
+            T acc = T(0);
+#pragma unroll
+            for (int s = 0; s < NT; ++s) acc = fma(e[s], xr[pr * W3 + s], acc);
+            x3[pr * 64 + lane] = acc;
+        }
+    }
+
+    __device__ __forceinline__ void fill_x3(int kind) const {
+        const bool band3 = ((sp.band >> 2) & 1) && b3 >= P && b3 + R + P <= sp.n[2];
+        if (band3) dir3<true>(kind);
+        else dir3<false>(kind);
+    }
+
+    // Step 3 for node q2 of the wave's row i2: X[v][j1] = sum_s t2[v][q2 S + s] X3[j1, i2l + s, lane]
+    // for NV second-direction tables t2[v] sharing the LDS reads.
+    template <bool BAND, int NV>
+    __device__ __forceinline__ void dir2(const uptr<T> (&t2)[NV], int q2, T (&X)[NV][W1]) const {
+        constexpr int NT = BAND ? P + 1 : S;
+        const int s0 = BAND ? q2 : 0;
+        const T *col = x3 + (wave + s0) * 64 + lane;
+#pragma unroll
+        for (int l1 = 0; l1 < W1; ++l1) {
+            T g[NT];
+#pragma unroll
+            for (int s = 0; s < NT; ++s) g[s] = col[(l1 * W2 + s) * 64];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T acc = T(0);
+#pragma unroll
+                for (int s = 0; s < NT; ++s) acc = fma(t2[v][q2 * S + s0 + s], g[s], acc);
+                X[v][l1] = acc;
+            }
+        }
+    }
+
+    // The coefficient samples of node q2 of the wave's row i2 (clamped into the space: i2c),
+    // for the block's rows b1 + i1l, nodes q1 and the lane's point g3: fv[v][i1l][q1]
+    // (0 for points outside the space).
+    template <int NV>
+    __device__ __forceinline__ void load(const T *const (&f)[NV], int q2, int64_t i2c, bool in2,
+                                         T (&fv)[NV][B1][Q]) const {
+        const int64_t n1 = sp.n[0], n2 = sp.n[1], n3 = sp.n[2];
+#pragma unroll
+        for (int i1l = 0; i1l < B1; ++i1l) {
+            const int64_t i1 = b1 + i1l;
+            const bool in = in2 && i1 < n1;
+            const int64_t i1c = i1 < n1 ? i1 : n1 - 1;
+            int64_t off, dq1;          // sample (i1, q1 = 0; i2, q2; g3) and the step in q1
+            if (sp.rows) {
+                off = ((i1c * n2 + i2c) * n3 + b3 + i3l) * (Q * Q * Q) + q2 * Q + q3;
+                dq1 = Q * Q;
+            } else {
+                off = ((i1c * Q) * sp.N[1] + i2c * Q + q2) * sp.ld + b3 * Q + lane;
+                dq1 = sp.N[1] * sp.ld;
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int q1 = 0; q1 < Q; ++q1) fv[v][i1l][q1] = in ? f[v][off + q1 * dq1] : T(0);
+        }
+    }
+
+    // Step 4 for the wave's row i2 and node q2: adds to acc[i1l] (rows b1 + i1l) the terms
+    // sum_q1 f_v(g) u_v(g), u_v = sum_s t1[v][...] X[v][i1l + s], over the NV terms.
+    template <int NV>
+    __device__ __forceinline__ void dir1(const uptr<T> (&t1)[NV], const T (&fv)[NV][B1][Q], const T (&X)[NV][W1],
+                                         T (&acc)[B1]) const {
+        const int64_t n1 = sp.n[0];
+        const int band1 = sp.band & 1;
+#pragma unroll
+        for (int i1l = 0; i1l < B1; ++i1l) {
+            const int64_t i1 = b1 + i1l;
+            const int64_t i1c = i1 < n1 ? i1 : n1 - 1;
+            if (interior<P>(band1, i1, n1)) {
+#pragma unroll
+                for (int q1 = 0; q1 < Q; ++q1)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const uptr<T> tr = t1[v] + (i1c * Q + q1) * S + q1;
+                        T u = T(0);
+#pragma unroll
+                        for (int s = 0; s <= P; ++s) u = fma(tr[s], X[v][i1l + q1 + s], u);
+                        acc[i1l] = fma(fv[v][i1l][q1], u, acc[i1l]);
+                    }
+            } else {
+#pragma unroll
+                for (int q1 = 0; q1 < Q; ++q1)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const uptr<T> tr = t1[v] + (i1c * Q + q1) * S;
+                        T u = T(0);
+#pragma unroll
+                        for (int s = 0; s < S; ++s) u = fma(tr[s], X[v][i1l + s], u);
+                        acc[i1l] = fma(fv[v][i1l][q1], u, acc[i1l]);
+                    }
+            }
+        }
+    }
+
+    // Step 1: the window of x, [W1][W2][W3] from (b1 - p, b2 - p, b3 - p), zero outside the
+    // space, by the whole work-group (the caller synchronizes).
+    __device__ __forceinline__ void stage_window(const T *__restrict__ x, T *win) const {
+        const int64_t n1 = sp.n[0], n2 = sp.n[1], n3 = sp.n[2];
+        for (int e = wave * 64 + lane; e < NX; e += 64 * kBlockWaves) {
+            const int l3 = e % W3, pr = e / W3, l2 = pr % W2, l1 = pr / W2;
+            const int64_t j1 = b1 - P + l1, j2 = b2 - P + l2, j3 = b3 - P + l3;
+            T v = T(0);
+            if (j1 >= 0 && j1 < n1 && j2 >= 0 && j2 < n2 && j3 >= 0 && j3 < n3) v = x[(j1 * n2 + j2) * n3 + j3];
+            win[e] = v;
+        }
+    }
+
+    // The wave's second-direction row, clamped into the space.
+    __device__ __forceinline__ int64_t row2() const {
+        const int64_t i2 = b2 + wave;
+        return i2 < sp.n[1] ? i2 : sp.n[1] - 1;
+    }
+
+    // Steps 3 and 4 over the wave's row i2, node by node, for NV terms sharing X3.  fv holds
+    // the samples of node q2 = 0 (loaded by the caller, ahead of the barrier); each node's
+    // loop loads the next node's samples before its own contraction, so that they are in
+    // flight meanwhile.
+    template <int NV>
+    __device__ __forceinline__ void pass(const uptr<T> (&t2)[NV], const uptr<T> (&t1)[NV], const T *const (&f)[NV],
+                                         bool in2, T (&fv)[NV][B1][Q], T (&acc)[B1]) const {
+        const int64_t n2 = sp.n[1];
+        const int64_t i2 = b2 + wave, i2c = row2();
+        const bool band2 = interior<P>((sp.band >> 1) & 1, i2, n2);
+        uptr<T> t2r[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) t2r[v] = t2[v] + i2c * (Q * S);
+#pragma unroll 1
+        for (int q2 = 0; q2 < Q; ++q2) {
+            T fn[NV][B1][Q];
+            if (q2 + 1 < Q) load<NV>(f, q2 + 1, i2c, in2, fn);
+            T X[NV][W1];
+            if (band2) dir2<true, NV>(t2r, q2, X);
+            else dir2<false, NV>(t2r, q2, X);
+            dir1<NV>(t1, fv, X, acc);
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int i1l = 0; i1l < B1; ++i1l)
+#pragma unroll
+                    for (int q1 = 0; q1 < Q; ++q1) fv[v][i1l][q1] = fn[v][i1l][q1];
+        }
+    }
+
+    // Steps 3 and 4 with every node's samples already in registers (fall[q2]); the node
+    // loop is unrolled.
+    template <int NV>
+    __device__ __forceinline__ void pass_all(const uptr<T> (&t2)[NV], const uptr<T> (&t1)[NV],
+                                             const T (&fall)[Q][NV][B1][Q], T (&acc)[B1]) const {
+        const int64_t n2 = sp.n[1];
+        const int64_t i2 = b2 + wave, i2c = row2();
+        const bool band2 = interior<P>((sp.band >> 1) & 1, i2, n2);
+        uptr<T> t2r[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) t2r[v] = t2[v] + i2c * (Q * S);
+#pragma unroll
+        for (int q2 = 0; q2 < Q; ++q2) {
+            T X[NV][W1];
+            if (band2) dir2<true, NV>(t2r, q2, X);
+            else dir2<false, NV>(t2r, q2, X);
+            dir1<NV>(t1, fall[q2], X, acc);
+        }
+    }
+};
+
+// FP64 y = M x loads all of a lane's samples before staging the window (they are in
+// flight during the first two steps: 0.83 against 0.86 ms at 160^3); the other products
+// load one node q2 ahead (FP32 y = M x loading everything first: 0.387 against 0.363 ms)
+constexpr bool kPreloadMassF64 = true;
+
+template <typename T, int P, int WHAT, int B1>
+__global__ __launch_bounds__(64 * kBlockWaves) void apply_block_kernel(DevSpace sp, DevTabs tb, const T *__restrict__ cf,
+                                                                      const T *__restrict__ a0,
+                                                                      const T *__restrict__ a1,
+                                                                      const T *__restrict__ a2,
+                                                                      const T *__restrict__ x, T *__restrict__ y,
+                                                                      int64_t blk0, int64_t n_blocks, int64_t nb2,
+                                                                      int64_t nb3) {
+    using B = Block<T, P, WHAT, B1>;
+    constexpr int Q = B::Q, R = B::R;
+    __shared__ __align__(16) T xw[B::NX];
+    __shared__ __align__(16) T x3[B::NPAIR * 64];
+    const int64_t blk = blk0 + block_order();
+    if (blk >= n_blocks) return;                                   // the whole work-group
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t n1 = sp.n[0], n2 = sp.n[1], n3 = sp.n[2];
+    const int64_t bb3 = blk % nb3, rest = blk / nb3;
+    const int64_t b1 = (rest / nb2) * B1, b2 = (rest % nb2) * kBlockWaves, b3 = bb3 * R;
+
+    // lane = g3 - b3 Q: row b3 + i3l, node q3 (with Q = 3 the last lane has no row)
+    const bool lane_row = lane < R * Q;
+    const int i3l = lane_row ? lane / Q : R - 1, q3 = lane_row ? lane - (lane / Q) * Q : 0;
+    const int64_t i3 = b3 + i3l;
+    const bool lane_in = lane_row && i3 < n3;
+    const B blk_ctx{sp, tb, xw, x3, b1, b2, b3, wave, lane, i3l, q3, i3 < n3 ? i3 : n3 - 1};
+    const int64_t i2c = blk_ctx.row2();
+    const bool in2 = lane_in && b2 + wave < n2;
+
+    T acc[B1];
+#pragma unroll
+    for (int k = 0; k < B1; ++k) acc[k] = T(0);
+    if constexpr (WHAT == kWhatM) {
+        const T *const f[1] = {cf};
+        const uptr<T> t2[1] = {utable<T>(tb, 0, 1)}, t1[1] = {utable<T>(tb, 0, 0)};
+        if constexpr (kPreloadMassF64 && sizeof(T) == 8) {
+            T fall[Q][1][B1][Q];
+#pragma unroll
+            for (int q2 = 0; q2 < Q; ++q2) blk_ctx.template load<1>(f, q2, i2c, in2, fall[q2]);
+            blk_ctx.stage_window(x, xw);
+            __syncthreads();
+            blk_ctx.fill_x3(0);
+            __syncthreads();
+            blk_ctx.template pass_all<1>(t2, t1, fall, acc);
+        } else {
+            T fv[1][B1][Q];
+            blk_ctx.template load<1>(f, 0, i2c, in2, fv);
+            blk_ctx.stage_window(x, xw);
+            __syncthreads();
+            blk_ctx.fill_x3(0);
+            __syncthreads();
+            blk_ctx.template pass<1>(t2, t1, f, in2, fv, acc);
+        }
+    } else {
+        // terms 1 and 2 (mass table in direction 3)
+        {
+            const T *const f[2] = {a0, a1};
+            T fv[2][B1][Q];
+            blk_ctx.template load<2>(f, 0, i2c, in2, fv);
+            blk_ctx.stage_window(x, xw);
+            __syncthreads();
+            blk_ctx.fill_x3(0);
+            __syncthreads();
+            const uptr<T> t2[2] = {utable<T>(tb, 0, 1), utable<T>(tb, 1, 1)};
+            const uptr<T> t1[2] = {utable<T>(tb, 1, 0), utable<T>(tb, 0, 0)};
+            blk_ctx.template pass<2>(t2, t1, f, in2, fv, acc);
+        }
+        // term 3 (stiffness table in direction 3)
+        {
+            const T *const f[1] = {a2};
+            T fv[1][B1][Q];
+            blk_ctx.template load<1>(f, 0, i2c, in2, fv);
+            __syncthreads();                                       // X3 is refilled
+            blk_ctx.fill_x3(1);
+            __syncthreads();
+            const uptr<T> t2[1] = {utable<T>(tb, 0, 1)}, t1[1] = {utable<T>(tb, 0, 0)};
+            blk_ctx.template pass<1>(t2, t1, f, in2, fv, acc);
+        }
+    }
+
+    // each row's value: the sum over its Q lanes (lanes i3l Q .. i3l Q + Q - 1)
+    const int base = i3l * Q;
+    const int64_t i2 = b2 + wave;
+#pragma unroll
+    for (int i1l = 0; i1l < B1; ++i1l) {
+        T sum = acc[i1l];
+#pragma unroll
+        for (int k = 1; k < Q; ++k) sum += __shfl(acc[i1l], base + k, 64);
+        const int64_t i1 = b1 + i1l;
+        if (lane_in && lane == base && i1 < n1 && i2 < n2) y[(i1 * n2 + i2) * n3 + i3] = sum;
+    }
+}
+
+// B1 (block rows along direction 1): 4 in FP32 (34 KB of LDS per work-group with p = 3,
+// four work-groups per CU), 2 in FP64 (55 KB, two per CU).  B1 = 1 measured slower in
+// both (more window pairs per row: 0.52 against 0.37 ms for FP32 y = M x), B1 = 2 in FP32
+// no faster.
+template <typename T>
+constexpr int block_b1() {
+    return sizeof(T) == 4 ? 4 : 2;
+}
+
+template <typename T, int P, int WHAT>
+hipError_t run_block(const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a, const void *x,
+                     void *y, hipStream_t st, int64_t max_tasks) {
+    constexpr int B1 = block_b1<T>(), R = 64 / (P + 1);
+    const int64_t nb1 = (sp.n[0] + B1 - 1) / B1, nb2 = (sp.n[1] + kBlockWaves - 1) / kBlockWaves;
+    const int64_t nb3 = (sp.n[2] + R - 1) / R;
+    const int64_t blocks = nb1 * nb2 * nb3;
+    // max_tasks counts waves: at most max_tasks / 4 work-groups (at least one) per dispatch
+    const int64_t step = std::max<int64_t>(1, max_tasks / kBlockWaves);
+    const T *a0 = nullptr, *a1 = nullptr, *a2 = nullptr;
+    if (WHAT == kWhatK) {
+        a0 = (const T *)a[0];
+        a1 = (const T *)a[1];
+        a2 = (const T *)a[2];
+    }
+    for (int64_t b0 = 0; b0 < blocks; b0 += step) {
+        const int64_t here = std::min(step, blocks - b0);
+        hipLaunchKernelGGL((apply_block_kernel<T, P, WHAT, B1>), dim3((unsigned)here), dim3(64 * kBlockWaves), 0, st,
+                           sp, tb, (const T *)c, a0, a1, a2, (const T *)x, (T *)y, b0, blocks, nb2, nb3);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T, int P>
+hipError_t run_block_what(int what, const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a,
+                          const void *x, void *y, hipStream_t st, int64_t max_tasks) {
+    if (what == kWhatM) return run_block<T, P, kWhatM>(sp, tb, c, a, x, y, st, max_tasks);
+    return run_block<T, P, kWhatK>(sp, tb, c, a, x, y, st, max_tasks);
+}
+
+}  // namespace
+
+hipError_t launch_apply_blocked(int dtype, int what, const DevSpace &sp, const DevTabs &tb, const void *c,
+                                const void *const *a, const void *x, void *y, hipStream_t stream, int64_t max_tasks) {
+    if (sp.d != 3 || (what != kWhatM && what != kWhatK)) return hipErrorInvalidValue;
+    if (dtype == 0)
+        return sp.p == 2 ? run_block_what<float, 2>(what, sp, tb, c, a, x, y, stream, max_tasks)
+                         : run_block_what<float, 3>(what, sp, tb, c, a, x, y, stream, max_tasks);
+    return sp.p == 2 ? run_block_what<double, 2>(what, sp, tb, c, a, x, y, stream, max_tasks)
+                     : run_block_what<double, 3>(what, sp, tb, c, a, x, y, stream, max_tasks);
+}
+
+}  // namespace wqa

@@ -17,8 +17,10 @@ pytestmark = pytest.mark.gpu
 
 TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
 
+# 3D: ragged blocks of rows in every direction; the last two also have blocks whose rows
+# are all interior along the last direction (its banded loops)
 SMALL = [(2, 2, (3, 4)), (2, 2, (5, 21)), (2, 3, (7, 23)), (3, 2, (4, 3, 21)), (3, 3, (4, 4, 4)),
-         (3, 3, (6, 7, 23))]
+         (3, 3, (6, 7, 23)), (3, 3, (6, 9, 40)), (3, 2, (5, 7, 47))]
 
 
 @pytest.fixture(scope="module")
