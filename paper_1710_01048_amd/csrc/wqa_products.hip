@@ -15,14 +15,15 @@
 //      space, goes to LDS;
 //   2. direction 3: X3[j1, j2, g3] = sum_s E_3[g3, s] x[j1, j2, s] for every window pair
 //      (j1, j2) and each of the block's R Q last-direction points (lane = g3), into LDS;
-//   3. direction 2 (wave w takes second-direction row i2 = b2 + w, node by node):
-//      X23[j1] = sum_s E_2[g2, s] X3[j1, s, g3] in registers;
-//   4. direction 1: u(g1, g2, g3) = sum_s E_1[g1, s] X23[s], times the coefficient sample
-//      of the point, summed over the row's nodes in q1 and q2 in registers and over q3
-//      across the row's Q lanes.
+//   3. direction 2 (wave w takes second-direction row i2 = b2 + w): X23[g2, j1] =
+//      sum_s E_2[g2, s] X3[j1, s, g3] for the row's Q nodes g2, in registers;
+//   4. direction 1, block row by block row (b1 + i1l): u(g1, g2, g3) = sum_s E_1[g1, s]
+//      X23[g2, s], times the coefficient sample of the point, summed over the row's nodes
+//      in q1 and q2 in registers and over q3 across the row's Q lanes.  A block row's
+//      samples are all of a lane's Q^2 points of it, loaded together one block row ahead.
 // Stiffness term k takes the stiffness table in direction k and the mass tables
-// elsewhere: terms 1 and 2 share X3 of the mass table, term 3 has its own (the same LDS
-// buffer, refilled).  Rows at least p from both ends of a direction whose tables are
+// elsewhere, one term at a time: terms 1 and 2 read X3 of the mass table, term 3 its own
+// (the same LDS buffer, refilled).  Rows at least p from both ends of a direction whose tables are
 // banded (DevSpace::band) take the P + 1 entries s = q .. q + p of each node; the others
 // all S.  The sums equal the per-row ones up to rounding order.
 #include "wqa_internal.h"
@@ -46,9 +47,10 @@ constexpr int kBlockWaves = 4;      // B2: the block's rows along direction 2, o
 // with its own L2; 0 keeps that order, 1 gives each XCD runs of kRun consecutive blocks
 // (the incomplete last run unchanged), 2 one contiguous share of the dispatch per XCD.
 // Consecutive blocks share the cache lines of their x windows and of their sample runs.
-// At 160^3, p = 3: runs of 8 took 0.355 / 0.815 ms (FP32 y = M x / y = K x) and 0.763 /
-// 1.896 ms (FP64), against 0.367 / 0.846 and 0.828 / 1.938 in dispatch order; runs of 2
-// and one share per XCD fell in between.
+// Measured at 160^3, p = 3, on an earlier form of this kernel (samples loaded node q2 by
+// node q2): runs of 8 took 0.355 / 0.815 ms (FP32 y = M x / y = K x) and 0.763 / 1.896 ms
+// (FP64), against 0.367 / 0.846 and 0.828 / 1.938 in dispatch order; runs of 2 and one
+// share per XCD fell in between.
 constexpr int kOrder = 1;
 constexpr uint32_t kRun = 8;
 
@@ -107,88 +109,108 @@ struct Block {
         else dir3<false>(kind);
     }
 
-    // Step 3 for node q2 of the wave's row i2: X[v][j1] = sum_s t2[v][q2 S + s] X3[j1, i2l + s, lane]
-    // for NV second-direction tables t2[v] sharing the LDS reads.
-    template <bool BAND, int NV>
-    __device__ __forceinline__ void dir2(const uptr<T> (&t2)[NV], int q2, T (&X)[NV][W1]) const {
+    // Step 3 for node q2 of the wave's row i2: X[j1] = sum_s t2[q2 S + s] X3[j1, i2l + s, lane].
+    template <bool BAND>
+    __device__ __forceinline__ void dir2(uptr<T> t2, int q2, T (&X)[W1]) const {
         constexpr int NT = BAND ? P + 1 : S;
         const int s0 = BAND ? q2 : 0;
         const T *col = x3 + (wave + s0) * 64 + lane;
 #pragma unroll
         for (int l1 = 0; l1 < W1; ++l1) {
-            T g[NT];
+            T acc = T(0);
 #pragma unroll
-            for (int s = 0; s < NT; ++s) g[s] = col[(l1 * W2 + s) * 64];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                T acc = T(0);
-#pragma unroll
-                for (int s = 0; s < NT; ++s) acc = fma(t2[v][q2 * S + s0 + s], g[s], acc);
-                X[v][l1] = acc;
-            }
+            for (int s = 0; s < NT; ++s) acc = fma(t2[q2 * S + s0 + s], col[(l1 * W2 + s) * 64], acc);
+            X[l1] = acc;
         }
     }
 
-    // The coefficient samples of node q2 of the wave's row i2 (clamped into the space: i2c),
-    // for the block's rows b1 + i1l, nodes q1 and the lane's point g3: fv[v][i1l][q1]
-    // (0 for points outside the space).
-    template <int NV>
-    __device__ __forceinline__ void load(const T *const (&f)[NV], int q2, int64_t i2c, bool in2,
-                                         T (&fv)[NV][B1][Q]) const {
+    // The coefficient samples of block row b1 + i1l in the wave's row i2 (clamped into the
+    // space: i2c) at the lane's last-direction point: fv[q1][q2] (0 outside the space).  In
+    // the row layout these are the lane's Q^2 values of a 4 Q^3-byte row block whose other
+    // values the row's other lanes load at the same time.
+    __device__ __forceinline__ void load(const T *__restrict__ f, int i1l, int64_t i2c, bool in2,
+                                         T (&fv)[Q][Q]) const {
         const int64_t n1 = sp.n[0], n2 = sp.n[1], n3 = sp.n[2];
+        const int64_t i1 = b1 + i1l;
+        const bool in = in2 && i1 < n1;
+        const int64_t i1c = i1 < n1 ? i1 : n1 - 1;
+        int64_t off, dq1, dq2;         // sample (i1, q1 = 0; i2, q2 = 0; g3) and the steps
+        if (sp.rows) {
+            off = ((i1c * n2 + i2c) * n3 + b3 + i3l) * (Q * Q * Q) + q3;
+            dq1 = Q * Q;
+            dq2 = Q;
+        } else {
+            off = ((i1c * Q) * sp.N[1] + i2c * Q) * sp.ld + b3 * Q + lane;
+            dq1 = sp.N[1] * sp.ld;
+            dq2 = sp.ld;
+        }
 #pragma unroll
-        for (int i1l = 0; i1l < B1; ++i1l) {
-            const int64_t i1 = b1 + i1l;
-            const bool in = in2 && i1 < n1;
-            const int64_t i1c = i1 < n1 ? i1 : n1 - 1;
-            int64_t off, dq1;          // sample (i1, q1 = 0; i2, q2; g3) and the step in q1
-            if (sp.rows) {
-                off = ((i1c * n2 + i2c) * n3 + b3 + i3l) * (Q * Q * Q) + q2 * Q + q3;
-                dq1 = Q * Q;
-            } else {
-                off = ((i1c * Q) * sp.N[1] + i2c * Q + q2) * sp.ld + b3 * Q + lane;
-                dq1 = sp.N[1] * sp.ld;
-            }
+        for (int q1 = 0; q1 < Q; ++q1)
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
+            for (int q2 = 0; q2 < Q; ++q2) fv[q1][q2] = in ? f[off + q1 * dq1 + q2 * dq2] : T(0);
+    }
+
+    // Step 4 for block row b1 + i1l: adds sum_{q2, q1} f(g) u(g) to acc, with
+    // u = sum_s t1[(i1 Q + q1) S + s] X[q2][i1l + s].
+    __device__ __forceinline__ void dir1(uptr<T> t1, int i1l, const T (&fv)[Q][Q], const T (&X)[Q][W1],
+                                         T &acc) const {
+        const int64_t n1 = sp.n[0];
+        const int64_t i1 = b1 + i1l;
+        const int64_t i1c = i1 < n1 ? i1 : n1 - 1;
+        if (interior<P>(sp.band & 1, i1, n1)) {
 #pragma unroll
-                for (int q1 = 0; q1 < Q; ++q1) fv[v][i1l][q1] = in ? f[v][off + q1 * dq1] : T(0);
+            for (int q2 = 0; q2 < Q; ++q2)
+#pragma unroll
+                for (int q1 = 0; q1 < Q; ++q1) {
+                    const uptr<T> tr = t1 + (i1c * Q + q1) * S + q1;
+                    T u = T(0);
+#pragma unroll
+                    for (int s = 0; s <= P; ++s) u = fma(tr[s], X[q2][i1l + q1 + s], u);
+                    acc = fma(fv[q1][q2], u, acc);
+                }
+        } else {
+#pragma unroll
+            for (int q2 = 0; q2 < Q; ++q2)
+#pragma unroll
+                for (int q1 = 0; q1 < Q; ++q1) {
+                    const uptr<T> tr = t1 + (i1c * Q + q1) * S;
+                    T u = T(0);
+#pragma unroll
+                    for (int s = 0; s < S; ++s) u = fma(tr[s], X[q2][i1l + s], u);
+                    acc = fma(fv[q1][q2], u, acc);
+                }
         }
     }
 
-    // Step 4 for the wave's row i2 and node q2: adds to acc[i1l] (rows b1 + i1l) the terms
-    // sum_q1 f_v(g) u_v(g), u_v = sum_s t1[v][...] X[v][i1l + s], over the NV terms.
-    template <int NV>
-    __device__ __forceinline__ void dir1(const uptr<T> (&t1)[NV], const T (&fv)[NV][B1][Q], const T (&X)[NV][W1],
+    // Steps 3 and 4 of one term over the wave's row i2: direction 2 for every node q2, then
+    // block row by block row the samples and direction 1.  Each block row's samples are
+    // loaded one row ahead (the first before direction 2), so that they are in flight during
+    // the contraction, and every sample line is used by back-to-back loads.  (Loads issued
+    // before a work-group barrier gain nothing: the barrier waits for them.)
+    __device__ __forceinline__ void pass(uptr<T> t2, uptr<T> t1, const T *__restrict__ f, bool in2,
                                          T (&acc)[B1]) const {
-        const int64_t n1 = sp.n[0];
-        const int band1 = sp.band & 1;
+        const int64_t n2 = sp.n[1];
+        const int64_t i2 = b2 + wave, i2c = row2();
+        const bool band2 = interior<P>((sp.band >> 1) & 1, i2, n2);
+        const uptr<T> t2r = t2 + i2c * (Q * S);
+        T fv[Q][Q];
+        load(f, 0, i2c, in2, fv);
+        T X[Q][W1];
+#pragma unroll
+        for (int q2 = 0; q2 < Q; ++q2) {
+            if (band2) dir2<true>(t2r, q2, X[q2]);
+            else dir2<false>(t2r, q2, X[q2]);
+        }
 #pragma unroll
         for (int i1l = 0; i1l < B1; ++i1l) {
-            const int64_t i1 = b1 + i1l;
-            const int64_t i1c = i1 < n1 ? i1 : n1 - 1;
-            if (interior<P>(band1, i1, n1)) {
+            T fn[Q][Q];
+            if (i1l + 1 < B1) load(f, i1l + 1, i2c, in2, fn);
+            dir1(t1, i1l, fv, X, acc[i1l]);
+            if (i1l + 1 < B1) {
 #pragma unroll
                 for (int q1 = 0; q1 < Q; ++q1)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        const uptr<T> tr = t1[v] + (i1c * Q + q1) * S + q1;
-                        T u = T(0);
-#pragma unroll
-                        for (int s = 0; s <= P; ++s) u = fma(tr[s], X[v][i1l + q1 + s], u);
-                        acc[i1l] = fma(fv[v][i1l][q1], u, acc[i1l]);
-                    }
-            } else {
-#pragma unroll
-                for (int q1 = 0; q1 < Q; ++q1)
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        const uptr<T> tr = t1[v] + (i1c * Q + q1) * S;
-                        T u = T(0);
-#pragma unroll
-                        for (int s = 0; s < S; ++s) u = fma(tr[s], X[v][i1l + s], u);
-                        acc[i1l] = fma(fv[v][i1l][q1], u, acc[i1l]);
-                    }
+                    for (int q2 = 0; q2 < Q; ++q2) fv[q1][q2] = fn[q1][q2];
             }
         }
     }
@@ -211,62 +233,7 @@ struct Block {
         const int64_t i2 = b2 + wave;
         return i2 < sp.n[1] ? i2 : sp.n[1] - 1;
     }
-
-    // Steps 3 and 4 over the wave's row i2, node by node, for NV terms sharing X3.  fv holds
-    // the samples of node q2 = 0 (loaded by the caller, ahead of the barrier); each node's
-    // loop loads the next node's samples before its own contraction, so that they are in
-    // flight meanwhile.
-    template <int NV>
-    __device__ __forceinline__ void pass(const uptr<T> (&t2)[NV], const uptr<T> (&t1)[NV], const T *const (&f)[NV],
-                                         bool in2, T (&fv)[NV][B1][Q], T (&acc)[B1]) const {
-        const int64_t n2 = sp.n[1];
-        const int64_t i2 = b2 + wave, i2c = row2();
-        const bool band2 = interior<P>((sp.band >> 1) & 1, i2, n2);
-        uptr<T> t2r[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) t2r[v] = t2[v] + i2c * (Q * S);
-#pragma unroll 1
-        for (int q2 = 0; q2 < Q; ++q2) {
-            T fn[NV][B1][Q];
-            if (q2 + 1 < Q) load<NV>(f, q2 + 1, i2c, in2, fn);
-            T X[NV][W1];
-            if (band2) dir2<true, NV>(t2r, q2, X);
-            else dir2<false, NV>(t2r, q2, X);
-            dir1<NV>(t1, fv, X, acc);
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int i1l = 0; i1l < B1; ++i1l)
-#pragma unroll
-                    for (int q1 = 0; q1 < Q; ++q1) fv[v][i1l][q1] = fn[v][i1l][q1];
-        }
-    }
-
-    // Steps 3 and 4 with every node's samples already in registers (fall[q2]); the node
-    // loop is unrolled.
-    template <int NV>
-    __device__ __forceinline__ void pass_all(const uptr<T> (&t2)[NV], const uptr<T> (&t1)[NV],
-                                             const T (&fall)[Q][NV][B1][Q], T (&acc)[B1]) const {
-        const int64_t n2 = sp.n[1];
-        const int64_t i2 = b2 + wave, i2c = row2();
-        const bool band2 = interior<P>((sp.band >> 1) & 1, i2, n2);
-        uptr<T> t2r[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) t2r[v] = t2[v] + i2c * (Q * S);
-#pragma unroll
-        for (int q2 = 0; q2 < Q; ++q2) {
-            T X[NV][W1];
-            if (band2) dir2<true, NV>(t2r, q2, X);
-            else dir2<false, NV>(t2r, q2, X);
-            dir1<NV>(t1, fall[q2], X, acc);
-        }
-    }
 };
-
-// FP64 y = M x loads all of a lane's samples before staging the window (they are in
-// flight during the first two steps: 0.83 against 0.86 ms at 160^3); the other products
-// load one node q2 ahead (FP32 y = M x loading everything first: 0.387 against 0.363 ms)
-constexpr bool kPreloadMassF64 = true;
 
 template <typename T, int P, int WHAT, int B1>
 __global__ __launch_bounds__(64 * kBlockWaves) void apply_block_kernel(DevSpace sp, DevTabs tb, const T *__restrict__ cf,
@@ -294,58 +261,25 @@ __global__ __launch_bounds__(64 * kBlockWaves) void apply_block_kernel(DevSpace 
     const int64_t i3 = b3 + i3l;
     const bool lane_in = lane_row && i3 < n3;
     const B blk_ctx{sp, tb, xw, x3, b1, b2, b3, wave, lane, i3l, q3, i3 < n3 ? i3 : n3 - 1};
-    const int64_t i2c = blk_ctx.row2();
     const bool in2 = lane_in && b2 + wave < n2;
 
     T acc[B1];
 #pragma unroll
     for (int k = 0; k < B1; ++k) acc[k] = T(0);
+    blk_ctx.stage_window(x, xw);
+    __syncthreads();
+    blk_ctx.fill_x3(0);                                            // mass table in direction 3
+    __syncthreads();
     if constexpr (WHAT == kWhatM) {
-        const T *const f[1] = {cf};
-        const uptr<T> t2[1] = {utable<T>(tb, 0, 1)}, t1[1] = {utable<T>(tb, 0, 0)};
-        if constexpr (kPreloadMassF64 && sizeof(T) == 8) {
-            T fall[Q][1][B1][Q];
-#pragma unroll
-            for (int q2 = 0; q2 < Q; ++q2) blk_ctx.template load<1>(f, q2, i2c, in2, fall[q2]);
-            blk_ctx.stage_window(x, xw);
-            __syncthreads();
-            blk_ctx.fill_x3(0);
-            __syncthreads();
-            blk_ctx.template pass_all<1>(t2, t1, fall, acc);
-        } else {
-            T fv[1][B1][Q];
-            blk_ctx.template load<1>(f, 0, i2c, in2, fv);
-            blk_ctx.stage_window(x, xw);
-            __syncthreads();
-            blk_ctx.fill_x3(0);
-            __syncthreads();
-            blk_ctx.template pass<1>(t2, t1, f, in2, fv, acc);
-        }
+        blk_ctx.pass(utable<T>(tb, 0, 1), utable<T>(tb, 0, 0), cf, in2, acc);
     } else {
-        // terms 1 and 2 (mass table in direction 3)
-        {
-            const T *const f[2] = {a0, a1};
-            T fv[2][B1][Q];
-            blk_ctx.template load<2>(f, 0, i2c, in2, fv);
-            blk_ctx.stage_window(x, xw);
-            __syncthreads();
-            blk_ctx.fill_x3(0);
-            __syncthreads();
-            const uptr<T> t2[2] = {utable<T>(tb, 0, 1), utable<T>(tb, 1, 1)};
-            const uptr<T> t1[2] = {utable<T>(tb, 1, 0), utable<T>(tb, 0, 0)};
-            blk_ctx.template pass<2>(t2, t1, f, in2, fv, acc);
-        }
-        // term 3 (stiffness table in direction 3)
-        {
-            const T *const f[1] = {a2};
-            T fv[1][B1][Q];
-            blk_ctx.template load<1>(f, 0, i2c, in2, fv);
-            __syncthreads();                                       // X3 is refilled
-            blk_ctx.fill_x3(1);
-            __syncthreads();
-            const uptr<T> t2[1] = {utable<T>(tb, 0, 1)}, t1[1] = {utable<T>(tb, 0, 0)};
-            blk_ctx.template pass<1>(t2, t1, f, in2, fv, acc);
-        }
+        // terms 1 and 2 share X3 of the mass table; term 3 refills it with the stiffness table
+        blk_ctx.pass(utable<T>(tb, 0, 1), utable<T>(tb, 1, 0), a0, in2, acc);
+        blk_ctx.pass(utable<T>(tb, 1, 1), utable<T>(tb, 0, 0), a1, in2, acc);
+        __syncthreads();
+        blk_ctx.fill_x3(1);
+        __syncthreads();
+        blk_ctx.pass(utable<T>(tb, 0, 1), utable<T>(tb, 0, 0), a2, in2, acc);
     }
 
     // each row's value: the sum over its Q lanes (lanes i3l Q .. i3l Q + Q - 1)
@@ -362,9 +296,9 @@ __global__ __launch_bounds__(64 * kBlockWaves) void apply_block_kernel(DevSpace 
 }
 
 // B1 (block rows along direction 1): 4 in FP32 (34 KB of LDS per work-group with p = 3,
-// four work-groups per CU), 2 in FP64 (55 KB, two per CU).  B1 = 1 measured slower in
-// both (more window pairs per row: 0.52 against 0.37 ms for FP32 y = M x), B1 = 2 in FP32
-// no faster.
+// four work-groups per CU), 2 in FP64 (55 KB, two per CU).  On the earlier form of the
+// kernel, B1 = 1 measured slower in both (more window pairs per row: 0.52 against 0.37 ms
+// for FP32 y = M x) and B1 = 2 in FP32 no faster.
 template <typename T>
 constexpr int block_b1() {
     return sizeof(T) == 4 ? 4 : 2;
