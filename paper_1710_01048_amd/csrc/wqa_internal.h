@@ -45,7 +45,8 @@ hipError_t launch_adjoint(int dtype, int final_mode, int what, const DevSpace &s
                           void *dc, void *const *da, hipStream_t stream, int64_t max_tasks);
 
 // Matrix-free product y = M x (what = kWhatM, coefficient c) or y = K x (kWhatK,
-// coefficients a), or with ones = true the load vector y_i = integral c B_i (x unused).
+// coefficients a) in 2D, or with ones = true the load vector y_i = integral c B_i (x unused)
+// in 2D and 3D; 3D products return hipErrorInvalidValue (they run launch_apply_blocked).
 hipError_t launch_apply(int dtype, int what, bool ones, const DevSpace &sp, const DevTabs &tb,
                         const void *c, const void *const *a, const void *x, void *y, hipStream_t stream,
                         int64_t max_tasks);

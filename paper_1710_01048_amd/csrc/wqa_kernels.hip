@@ -1186,8 +1186,8 @@ __global__ __launch_bounds__(64 * WPB) void adjoint_kernel(
 
 
 // --------------------------------------------------------------------------------------
-// Matrix-free products y = M x, y = K x and the load vector.  Lane (r, q_d) as in the
-// adjoint.  The tile's window of x (every column any of its rows reaches: i_k - P ..
+// Matrix-free products y = M x, y = K x in 2D and the load vector (3D products: the
+// blocked kernel of wqa_products.hip).  Lane (r, q_d) as in the adjoint.  The tile's window of x (every column any of its rows reaches: i_k - P ..
 // i_k + P in each direction) is staged in LDS, zero outside the space.  Each lane
 // contracts the window over s_d, s_{d-1}, ..., s_1 into its node column -- at every point
 // of the row, sum_j T(i, q, j) x_j with the product of the directions' tables --
@@ -1366,9 +1366,10 @@ __global__ __launch_bounds__(64 * kApplyWaves, sizeof(T) == 4 ? 4 : 2) void appl
     if (task >= n_tasks) return;
     const Tile t = make_tile<D, P>(sp, task, tiles_per_line, R, Q, lane);
     // y = M x in FP64: the coefficient samples of the lane's points are loaded once the window
-    // is staged, so that they are in flight while it is contracted (0.92 against 1.22 ms at
-    // 160^3; 1.01 ms when loaded before the window, whose loads then waited behind them).  In
-    // FP32 either made y = M x 30% slower: 16 more registers cost two waves per SIMD there.
+    // is staged, so that they are in flight while it is contracted (measured in 3D at 160^3,
+    // when this kernel served the 3D products: 0.92 against 1.22 ms; 1.01 ms when loaded
+    // before the window, whose loads then waited behind them).  In FP32 either made y = M x
+    // 30% slower: 16 more registers cost two waves per SIMD there.
     constexpr int NQ2 = (D == 3) ? Q : 1;
     constexpr bool PRE = sizeof(T) == 8 && WHAT == kWhatM && !ONES;
     T pre[Q][NQ2];
@@ -1534,8 +1535,12 @@ template <typename T, int P, int D>
 hipError_t apply_what(int what, bool ones, const DevSpace &sp, const DevTabs &tb, const void *c,
                       const void *const *a, const void *x, void *y, hipStream_t st, int64_t max_tasks) {
     if (ones) return run_apply<T, P, D, kWhatM, true>(sp, tb, c, a, x, y, st, max_tasks);
-    if (what == kWhatM) return run_apply<T, P, D, kWhatM, false>(sp, tb, c, a, x, y, st, max_tasks);
-    return run_apply<T, P, D, kWhatK, false>(sp, tb, c, a, x, y, st, max_tasks);
+    if constexpr (D == 3) {
+        return hipErrorInvalidValue;              // the 3D products run launch_apply_blocked
+    } else {
+        if (what == kWhatM) return run_apply<T, P, D, kWhatM, false>(sp, tb, c, a, x, y, st, max_tasks);
+        return run_apply<T, P, D, kWhatK, false>(sp, tb, c, a, x, y, st, max_tasks);
+    }
 }
 
 template <typename T>
