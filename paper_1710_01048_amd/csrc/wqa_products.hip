@@ -26,6 +26,9 @@
 // (the same LDS buffer, refilled).  Rows at least p from both ends of a direction whose tables are
 // banded (DevSpace::band) take the P + 1 entries s = q .. q + p of each node; the others
 // all S.  The sums equal the per-row ones up to rounding order.
+// Loads are issued in the order of their use (they complete in order): the lane's
+// direction-3 table entries, the window, then the first samples, which stay in flight
+// through the direction-3 phase; the work-group barriers order LDS only.
 #include "wqa_internal.h"
 
 #include <algorithm>
@@ -44,26 +47,29 @@ __device__ __forceinline__ uptr<T> utable(const DevTabs &tb, int kind, int dir) 
 constexpr int kBlockWaves = 4;      // B2: the block's rows along direction 2, one per wave
 
 // Work-group order.  The hardware deals work-groups round-robin over the 8 XCDs, each
-// with its own L2; 0 keeps that order, 1 gives each XCD runs of kRun consecutive blocks
-// (the incomplete last run unchanged), 2 one contiguous share of the dispatch per XCD.
-// Consecutive blocks share the cache lines of their x windows and of their sample runs.
-// Measured at 160^3, p = 3, on an earlier form of this kernel (samples loaded node q2 by
-// node q2): runs of 8 took 0.355 / 0.815 ms (FP32 y = M x / y = K x) and 0.763 / 1.896 ms
-// (FP64), against 0.367 / 0.846 and 0.828 / 1.938 in dispatch order; runs of 2 and one
-// share per XCD fell in between.
-constexpr int kOrder = 1;
+// with its own L2; here each XCD takes runs of kRun consecutive blocks (the incomplete last
+// run keeps the hardware's order), so that neighbouring blocks, which share the cache lines
+// of their x windows and sample runs, meet in one L2.  Measured at 160^3, p = 3, on an
+// earlier form of this kernel (samples loaded node q2 by node q2): runs of 8 took 0.355 /
+// 0.815 ms (FP32 y = M x / y = K x) and 0.763 / 1.896 ms (FP64), against 0.367 / 0.846 and
+// 0.828 / 1.938 in the hardware's order; runs of 2 and one contiguous share per XCD fell in
+// between, runs of 16 (on the final form) within 2% of runs of 8.
 constexpr uint32_t kRun = 8;
 
 __device__ __forceinline__ uint32_t block_order() {
-    const uint32_t b = blockIdx.x, nb = gridDim.x;
-    if constexpr (kOrder == 1) {
-        const uint32_t span = 8u * kRun, full = nb / span * span;
-        return b >= full ? b : b - b % span + (b % 8) * kRun + (b / 8) % kRun;
-    } else if constexpr (kOrder == 2) {
-        const uint32_t q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
-        return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-    }
-    return b;
+    const uint32_t b = blockIdx.x, span = 8u * kRun, full = gridDim.x / span * span;
+    return b >= full ? b : b - b % span + (b % 8) * kRun + (b / 8) % kRun;
+}
+
+// Work-group barrier that orders LDS only: the global loads in flight (coefficient
+// samples) stay in flight across it.  The kernel writes global memory only at its end.
+// (__syncthreads() waits for every load in flight first; with it the first samples could
+// not be issued ahead, and the kernel took 0.343 / 0.758 ms for FP32 y = M x / y = K x
+// at 160^3 against 0.246 / 0.627.)
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 template <int P>
@@ -71,7 +77,7 @@ __device__ __forceinline__ bool interior(int band_bit, int64_t i, int64_t n) {
     return band_bit && i >= P && i < n - P;
 }
 
-template <typename T, int P, int WHAT, int B1>
+template <typename T, int P, int B1>
 struct Block {
     static constexpr int Q = P + 1, S = 2 * P + 1, R = 64 / Q, B2 = kBlockWaves;
     static constexpr int W1 = B1 + 2 * P, W2 = B2 + 2 * P, W3 = R + 2 * P;
@@ -86,14 +92,31 @@ struct Block {
     int wave, lane, i3l, q3;
     int64_t i3c;       // the lane's last-direction row, clamped into the space
 
-    // Step 2: X3 for every window pair, with the direction-3 table of kind `kind`.
-    template <bool BAND>
-    __device__ __forceinline__ void dir3(int kind) const {
-        constexpr int NT = BAND ? P + 1 : S;
-        const T *tr = (const T *)tb.t[kind][2] + (i3c * Q + q3) * S + (BAND ? q3 : 0);
-        T e[NT];
+    // Whether every row of the block is interior along direction 3 and its tables banded.
+    __device__ __forceinline__ bool band3() const {
+        return ((sp.band >> 2) & 1) && b3 >= P && b3 + R + P <= sp.n[2];
+    }
+
+    // The lane's direction-3 table entries of kind `kind`: e[s] = T_3[i3, q3, q3 + s] for
+    // s <= p (banded) or T_3[i3, q3, s] for every s.  Loaded before the samples: a later
+    // load would have to wait for them (loads complete in order).
+    __device__ __forceinline__ void table3(int kind, bool band, T (&e)[S]) const {
+        const T *tr = (const T *)tb.t[kind][2] + (i3c * Q + q3) * S;
+        if (band) {
 #pragma unroll
-        for (int s = 0; s < NT; ++s) e[s] = tr[s];
+            for (int s = 0; s <= P; ++s) e[s] = tr[q3 + s];
+#pragma unroll
+            for (int s = P + 1; s < S; ++s) e[s] = T(0);
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s) e[s] = tr[s];
+        }
+    }
+
+    // Step 2: X3 for every window pair, with the lane's direction-3 table entries e.
+    template <bool BAND>
+    __device__ __forceinline__ void dir3(const T (&e)[S]) const {
+        constexpr int NT = BAND ? P + 1 : S;
         const T *xr = xw + i3l + (BAND ? q3 : 0);
         for (int pr = wave; pr < NPAIR; pr += kBlockWaves) {
             T acc = T(0);
@@ -103,10 +126,9 @@ struct Block {
         }
     }
 
-    __device__ __forceinline__ void fill_x3(int kind) const {
-        const bool band3 = ((sp.band >> 2) & 1) && b3 >= P && b3 + R + P <= sp.n[2];
-        if (band3) dir3<true>(kind);
-        else dir3<false>(kind);
+    __device__ __forceinline__ void fill_x3(bool band, const T (&e)[S]) const {
+        if (band) dir3<true>(e);
+        else dir3<false>(e);
     }
 
     // Step 3 for node q2 of the wave's row i2: X[j1] = sum_s t2[q2 S + s] X3[j1, i2l + s, lane].
@@ -127,27 +149,32 @@ struct Block {
     // The coefficient samples of block row b1 + i1l in the wave's row i2 (clamped into the
     // space: i2c) at the lane's last-direction point: fv[q1][q2] (0 outside the space).  In
     // the row layout these are the lane's Q^2 values of a 4 Q^3-byte row block whose other
-    // values the row's other lanes load at the same time.
+    // values the row's other lanes load at the same time.  Every lane loads from indices
+    // clamped into the space and zeroes what lies outside afterwards: no branches, so all
+    // Q^2 loads are in flight at once.
     __device__ __forceinline__ void load(const T *__restrict__ f, int i1l, int64_t i2c, bool in2,
                                          T (&fv)[Q][Q]) const {
         const int64_t n1 = sp.n[0], n2 = sp.n[1], n3 = sp.n[2];
         const int64_t i1 = b1 + i1l;
         const bool in = in2 && i1 < n1;
         const int64_t i1c = i1 < n1 ? i1 : n1 - 1;
-        int64_t off, dq1, dq2;         // sample (i1, q1 = 0; i2, q2 = 0; g3) and the steps
+        int64_t off, dq1, dq2;         // sample (i1, q1 = 0; i2, q2 = 0; i3, q3) and the steps
         if (sp.rows) {
-            off = ((i1c * n2 + i2c) * n3 + b3 + i3l) * (Q * Q * Q) + q3;
+            off = ((i1c * n2 + i2c) * n3 + i3c) * (Q * Q * Q) + q3;
             dq1 = Q * Q;
             dq2 = Q;
         } else {
-            off = ((i1c * Q) * sp.N[1] + i2c * Q) * sp.ld + b3 * Q + lane;
+            off = ((i1c * Q) * sp.N[1] + i2c * Q) * sp.ld + i3c * Q + q3;
             dq1 = sp.N[1] * sp.ld;
             dq2 = sp.ld;
         }
 #pragma unroll
         for (int q1 = 0; q1 < Q; ++q1)
 #pragma unroll
-            for (int q2 = 0; q2 < Q; ++q2) fv[q1][q2] = in ? f[off + q1 * dq1 + q2 * dq2] : T(0);
+            for (int q2 = 0; q2 < Q; ++q2) {
+                const T v = f[off + q1 * dq1 + q2 * dq2];
+                fv[q1][q2] = in ? v : T(0);
+            }
     }
 
     // Step 4 for block row b1 + i1l: adds sum_{q2, q1} f(g) u(g) to acc, with
@@ -183,18 +210,18 @@ struct Block {
     }
 
     // Steps 3 and 4 of one term over the wave's row i2: direction 2 for every node q2, then
-    // block row by block row the samples and direction 1.  Each block row's samples are
-    // loaded one row ahead (the first before direction 2), so that they are in flight during
-    // the contraction, and every sample line is used by back-to-back loads.  (Loads issued
-    // before a work-group barrier gain nothing: the barrier waits for them.)
-    __device__ __forceinline__ void pass(uptr<T> t2, uptr<T> t1, const T *__restrict__ f, bool in2,
-                                         T (&acc)[B1]) const {
+    // block row by block row direction 1 with the samples.  fv holds block row 0's samples on
+    // entry (loaded by the caller ahead of the work before).  Each block row's loop loads
+    // the next one's (NEXT: after the last, block row 0 of the next term's field fnext, left
+    // in fv), so that they are in flight during the contraction, and every sample line is
+    // used by back-to-back loads.
+    template <bool NEXT>
+    __device__ __forceinline__ void pass(uptr<T> t2, uptr<T> t1, const T *__restrict__ f, const T *__restrict__ fnext,
+                                         bool in2, T (&fv)[Q][Q], T (&acc)[B1]) const {
         const int64_t n2 = sp.n[1];
         const int64_t i2 = b2 + wave, i2c = row2();
         const bool band2 = interior<P>((sp.band >> 1) & 1, i2, n2);
         const uptr<T> t2r = t2 + i2c * (Q * S);
-        T fv[Q][Q];
-        load(f, 0, i2c, in2, fv);
         T X[Q][W1];
 #pragma unroll
         for (int q2 = 0; q2 < Q; ++q2) {
@@ -205,8 +232,9 @@ struct Block {
         for (int i1l = 0; i1l < B1; ++i1l) {
             T fn[Q][Q];
             if (i1l + 1 < B1) load(f, i1l + 1, i2c, in2, fn);
+            else if (NEXT) load(fnext, 0, i2c, in2, fn);
             dir1(t1, i1l, fv, X, acc[i1l]);
-            if (i1l + 1 < B1) {
+            if (i1l + 1 < B1 || NEXT) {
 #pragma unroll
                 for (int q1 = 0; q1 < Q; ++q1)
 #pragma unroll
@@ -218,13 +246,23 @@ struct Block {
     // Step 1: the window of x, [W1][W2][W3] from (b1 - p, b2 - p, b3 - p), zero outside the
     // space, by the whole work-group (the caller synchronizes).
     __device__ __forceinline__ void stage_window(const T *__restrict__ x, T *win) const {
+        // every load of the thread first, then the LDS writes: one round trip, not NIT
         const int64_t n1 = sp.n[0], n2 = sp.n[1], n3 = sp.n[2];
-        for (int e = wave * 64 + lane; e < NX; e += 64 * kBlockWaves) {
+        constexpr int NT = 64 * kBlockWaves, NIT = (NX + NT - 1) / NT;
+        T v[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int e = wave * 64 + lane + it * NT;
             const int l3 = e % W3, pr = e / W3, l2 = pr % W2, l1 = pr / W2;
             const int64_t j1 = b1 - P + l1, j2 = b2 - P + l2, j3 = b3 - P + l3;
-            T v = T(0);
-            if (j1 >= 0 && j1 < n1 && j2 >= 0 && j2 < n2 && j3 >= 0 && j3 < n3) v = x[(j1 * n2 + j2) * n3 + j3];
-            win[e] = v;
+            v[it] = T(0);
+            if (e < NX && j1 >= 0 && j1 < n1 && j2 >= 0 && j2 < n2 && j3 >= 0 && j3 < n3)
+                v[it] = x[(j1 * n2 + j2) * n3 + j3];
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int e = wave * 64 + lane + it * NT;
+            if (e < NX) win[e] = v[it];
         }
     }
 
@@ -243,8 +281,8 @@ __global__ __launch_bounds__(64 * kBlockWaves) void apply_block_kernel(DevSpace 
                                                                       const T *__restrict__ x, T *__restrict__ y,
                                                                       int64_t blk0, int64_t n_blocks, int64_t nb2,
                                                                       int64_t nb3) {
-    using B = Block<T, P, WHAT, B1>;
-    constexpr int Q = B::Q, R = B::R;
+    using B = Block<T, P, B1>;
+    constexpr int Q = B::Q, R = B::R, S = B::S;
     __shared__ __align__(16) T xw[B::NX];
     __shared__ __align__(16) T x3[B::NPAIR * 64];
     const int64_t blk = blk0 + block_order();
@@ -266,20 +304,29 @@ __global__ __launch_bounds__(64 * kBlockWaves) void apply_block_kernel(DevSpace 
     T acc[B1];
 #pragma unroll
     for (int k = 0; k < B1; ++k) acc[k] = T(0);
+    // loads in order of use, since they complete in order: the direction-3 table entries,
+    // the window of x, then the first term's first samples, which stay in flight while x is
+    // contracted in direction 3
+    const bool band3 = blk_ctx.band3();
+    T e3[WHAT == kWhatM ? 1 : 2][S];
+    blk_ctx.table3(0, band3, e3[0]);
+    if constexpr (WHAT != kWhatM) blk_ctx.table3(1, band3, e3[WHAT == kWhatM ? 0 : 1]);
     blk_ctx.stage_window(x, xw);
-    __syncthreads();
-    blk_ctx.fill_x3(0);                                            // mass table in direction 3
-    __syncthreads();
+    T fv[Q][Q];
+    blk_ctx.load(WHAT == kWhatM ? cf : a0, 0, blk_ctx.row2(), in2, fv);
+    lds_barrier();
+    blk_ctx.fill_x3(band3, e3[0]);                                 // mass table in direction 3
+    lds_barrier();
     if constexpr (WHAT == kWhatM) {
-        blk_ctx.pass(utable<T>(tb, 0, 1), utable<T>(tb, 0, 0), cf, in2, acc);
+        blk_ctx.template pass<false>(utable<T>(tb, 0, 1), utable<T>(tb, 0, 0), cf, nullptr, in2, fv, acc);
     } else {
         // terms 1 and 2 share X3 of the mass table; term 3 refills it with the stiffness table
-        blk_ctx.pass(utable<T>(tb, 0, 1), utable<T>(tb, 1, 0), a0, in2, acc);
-        blk_ctx.pass(utable<T>(tb, 1, 1), utable<T>(tb, 0, 0), a1, in2, acc);
-        __syncthreads();
-        blk_ctx.fill_x3(1);
-        __syncthreads();
-        blk_ctx.pass(utable<T>(tb, 0, 1), utable<T>(tb, 0, 0), a2, in2, acc);
+        blk_ctx.template pass<true>(utable<T>(tb, 0, 1), utable<T>(tb, 1, 0), a0, a1, in2, fv, acc);
+        blk_ctx.template pass<true>(utable<T>(tb, 1, 1), utable<T>(tb, 0, 0), a1, a2, in2, fv, acc);
+        lds_barrier();
+        blk_ctx.fill_x3(band3, e3[WHAT == kWhatM ? 0 : 1]);        // stiffness table
+        lds_barrier();
+        blk_ctx.template pass<false>(utable<T>(tb, 0, 1), utable<T>(tb, 0, 0), a2, nullptr, in2, fv, acc);
     }
 
     // each row's value: the sum over its Q lanes (lanes i3l Q .. i3l Q + Q - 1)
