@@ -111,3 +111,33 @@ def test_products_160_cubed(wqa, dtype):
     eb = _product_error(b[ridx].cpu().numpy(), Mw, cols, np.ones_like(x))
     print(f"160^3 {dtype}: M x {eM:.2e}, K x {eK:.2e}, load {eb:.2e}")
     assert max(eM, eK, eb) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("case", [(3, 3, (4, 5, 3000)), (3, 3, (3000, 4, 5)), (3, 2, (4, 3000, 5))], ids=_ids)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_products_long_directions(wqa, case, dtype):
+    """3D products with one long direction (hundreds of row blocks along it, few across the
+    others): sampled rows covering both ends of every direction, against the oracle, in both
+    sample layouts (the same bits)."""
+    d, p, n_el = case
+    sp = wqa.Space(d, p, n_el)
+    recipe = ("fourier", 3)
+    f = ph.device_fields(sp, recipe, dtype)
+    g = torch.Generator(device=sp.device)
+    g.manual_seed(5007)
+    xd = torch.randn(sp.n_rows, generator=g, dtype=torch.float64, device=sp.device).to(dtype)
+    yM = sp.apply_mass(f[0], xd)
+    yK = sp.apply_stiffness(f[1:], xd)
+    rows = st.sample_rows(list(sp.n_basis), p, 200, seed=8)
+    cols = st.columns(list(sp.n_basis), p, rows)
+    x = xd.double().cpu().numpy()
+    ridx = torch.from_numpy(rows).to(sp.device)
+    Mw, Kw = ph.oracle_forward(p, n_el, rows, recipe)
+    eM = _product_error(yM[ridx].cpu().numpy(), Mw, cols, x)
+    eK = _product_error(yK[ridx].cpu().numpy(), Kw, cols, x)
+    print(f"long {_ids(case)} {dtype}: M x {eM:.2e}, K x {eK:.2e}")
+    assert max(eM, eK) <= TOL[dtype]
+    sp.set_sample_layout("rows")
+    fr = [sp.rows_from_grid(v) for v in f]
+    assert torch.equal(sp.apply_mass(fr[0], xd), yM)
+    assert torch.equal(sp.apply_stiffness(fr[1:], xd), yK)
