@@ -260,8 +260,9 @@ def matrix_free(sp, args):
             ms = e0.elapsed_time(e1) / 10
             nbytes = rows * (nf * Q ** 3 + (2 if terms else 1)) * b
             flops = 2.0 * rows * (macs[terms] if terms else Q ** 3)
-            res[name] = {"ms": ms, "GB_s": nbytes / (ms * 1e-3) / 1e9, "TFLOP_s": flops / (ms * 1e-3) / 1e12,
-                         "rows_per_s": rows / (ms * 1e-3)}
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            res[name] = {"ms": ms, "GB_s": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+                         "TFLOP_s": flops / (ms * 1e-3) / 1e12, "rows_per_s": rows / (ms * 1e-3)}
         out["fp32" if b == 4 else "fp64"] = res
         del fields, x, y
         torch.cuda.empty_cache()
