@@ -234,13 +234,13 @@ def matrix_free(sp, args):
     """Load vector and matrix-free products y = M x, y = K x on the same workload (FP32
     and FP64): event-timed per call, with algorithmic HBM bytes per row -- the samples of
     the fields read (Q^d each), x and y (one value each; x's band is re-read from cache)
-    -- and the multiply-adds the products' kernel issues per row (blocks of B1 x 4 x R
-    rows, B1 = 4 in FP32 and 2 in FP64, banded rows), in `product_macs`."""
+    -- and the multiply-adds the products' kernel issues per row (blocks of 4 x 4 x R rows,
+    banded rows), in `product_macs`."""
     out = {}
     Q, rows = P + 1, sp.n_rows
     for dtype in ((torch.float32,) if args.skip_fp64 else (torch.float32, torch.float64)):
         b = 4 if dtype == torch.float32 else 8
-        macs = {1: product_macs(P, 4 if b == 4 else 2, "M"), 3: product_macs(P, 4 if b == 4 else 2, "K")}
+        macs = {1: product_macs(P, 4, "M"), 3: product_macs(P, 4, "K")}
         fields, _, _ = make_inputs_fields(sp, dtype)
         g = torch.Generator(device=sp.device)
         g.manual_seed(5003)

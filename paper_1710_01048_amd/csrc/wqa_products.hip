@@ -342,13 +342,15 @@ __global__ __launch_bounds__(64 * kBlockWaves) void apply_block_kernel(DevSpace 
     }
 }
 
-// B1 (block rows along direction 1): 4 in FP32 (34 KB of LDS per work-group with p = 3,
-// four work-groups per CU), 2 in FP64 (55 KB, two per CU).  On the earlier form of the
-// kernel, B1 = 1 measured slower in both (more window pairs per row: 0.52 against 0.37 ms
-// for FP32 y = M x) and B1 = 2 in FP32 no faster.
+// B1 (block rows along direction 1): 4.  With p = 3 a work-group holds 34 KB of LDS in FP32
+// (four per CU) and 69 KB in FP64 (two per CU).  At 160^3, FP64 y = M x / y = K x took 0.48 /
+// 1.22-1.25 ms with B1 = 4, 0.52-0.53 / 1.24-1.26 with 3 and 0.60-0.61 / 1.32-1.36 with 2
+// (the same LDS per CU as FP32 then, but less of each block's load latency hidden per
+// work-group); in FP32, 2 was no faster and 3 slower.  B1 = 5 was within 3% either way in
+// both, and 6 or 8 in FP32 slower.
 template <typename T>
 constexpr int block_b1() {
-    return sizeof(T) == 4 ? 4 : 2;
+    return 4;
 }
 
 template <typename T, int P, int WHAT>
