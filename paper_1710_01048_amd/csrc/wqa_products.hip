@@ -345,18 +345,15 @@ __global__ __launch_bounds__(64 * kBlockWaves) void apply_block_kernel(DevSpace 
 // B1 (block rows along direction 1): 4.  With p = 3 a work-group holds 34 KB of LDS in FP32
 // (four per CU) and 69 KB in FP64 (two per CU).  At 160^3, FP64 y = M x / y = K x took 0.48 /
 // 1.22-1.25 ms with B1 = 4, 0.52-0.53 / 1.24-1.26 with 3 and 0.60-0.61 / 1.32-1.36 with 2
-// (the same LDS per CU as FP32 then, but less of each block's load latency hidden per
-// work-group); in FP32, 2 was no faster and 3 slower.  B1 = 5 was within 3% either way in
-// both, and 6 or 8 in FP32 slower.
-template <typename T>
-constexpr int block_b1() {
-    return 4;
-}
+// (two work-groups per CU in each case: smaller blocks hide less of their load latency);
+// in FP32, 2 was no faster and 3 slower.  B1 = 5 was within 3% either way in both, and 6
+// or 8 in FP32 slower.
+constexpr int kBlockRows1 = 4;
 
 template <typename T, int P, int WHAT>
 hipError_t run_block(const DevSpace &sp, const DevTabs &tb, const void *c, const void *const *a, const void *x,
                      void *y, hipStream_t st, int64_t max_tasks) {
-    constexpr int B1 = block_b1<T>(), R = 64 / (P + 1);
+    constexpr int B1 = kBlockRows1, R = 64 / (P + 1);
     const int64_t nb1 = (sp.n[0] + B1 - 1) / B1, nb2 = (sp.n[1] + kBlockWaves - 1) / kBlockWaves;
     const int64_t nb3 = (sp.n[2] + R - 1) / R;
     const int64_t blocks = nb1 * nb2 * nb3;
