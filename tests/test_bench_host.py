@@ -46,3 +46,16 @@ def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     other.write_text("// another kernel source\n")
     monkeypatch.setattr(bench, "KERNEL_SRC", str(other))
     assert bench.traffic_for("forward_fp32_mk", layout) is None
+
+
+def test_product_work_counts():
+    """The multiply-adds per row the bench assigns to the blocked products, counted by
+    hand for p = 3 and blocks of 4 x 4 x 16 rows on banded rows: the last direction over
+    10 x 10 window pairs (100 pairs x 64 points x 4 entries over 256 rows = 100 per table),
+    the second over 10 first-direction columns (4 nodes x 10 x 4 entries x 4 / 4 = 160 per
+    table), the first direction (64 points x 4 = 256 per term) and the samples (64 per term)."""
+    import bench
+    assert bench.product_macs(3, 4, "M") == 100 + 160 + 256 + 64
+    assert bench.product_macs(3, 4, "K") == 2 * 100 + 3 * 160 + 3 * (256 + 64)
+    # p = 2: 8 x 8 pairs, 3 nodes per direction
+    assert bench.product_macs(2, 4, "M") == 64 * 3 * 3 / 16 + 3 * 8 * 3 * 3 / 4 + 27 * 3 + 27
